@@ -1,0 +1,202 @@
+/*
+ * twoscale.h -- C ABI of the MI355X two-scale surrogate-stencil library.
+ *
+ * Method: Bauer, Mohr, Ruede, Weismueller, Wittmann, Wohlmuth, "A two-scale
+ * approach for efficient on-the-fly operator assembly in massively parallel
+ * high performance multigrid codes" (arXiv 1608.06473).  The library solves
+ * -Laplace(u) = f on a spherical shell with u = 0 on the boundary (Sec. 2.1,
+ * eq. model_eq) with P1 finite elements on hierarchically refined macro
+ * tetrahedra mapped by a blending function (Sec. 2.2), and replaces the
+ * on-the-fly element assembly of the 15-point volume stencils by surrogate
+ * polynomials fitted per macro and level (Sec. 3).
+ *
+ * Conventions used by every call:
+ *  - level: N = 2^level fine intervals per macro edge (the paper's level l
+ *    is level - 2; level 2 has one interior node per macro and is the
+ *    coarsest multigrid level).  Valid levels are 2..9.
+ *  - Vector layout ("block layout"): macro-major; inside macro m all
+ *    (N+1)(N+2)(N+3)/6 nodes (i, j, k) >= 0, i + j + k <= N, plane k outer,
+ *    row j, index i inner:
+ *        slot = m * B + (tet(N+1) - tet(N+1-k)) + j (N+1-k) - j (j-1)/2 + i,
+ *    tet(n) = n (n+1) (n+2) / 6, B = tet(N+1).  Macro m's fine node (i,j,k)
+ *    has barycentric weights (N-i-j-k, i, j, k)/N of its vertices in the
+ *    order given to ts_mesh_create.  Nodes on faces, edges and vertices of
+ *    the macro mesh appear once in every macro that contains them; library
+ *    calls take inputs whose copies agree and keep outputs that way.
+ *    Dirichlet nodes (on a face of the mesh boundary) hold 0.
+ *  - Canonical order (for exchange with other codes): vertices by id; edges
+ *    (g0 < g1) lexicographic, points a = 1..N-1 (weight of g1 = a/N); faces
+ *    (g0 < g1 < g2) lexicographic, points b = 1..N-2, a = 1..N-1-b (weights
+ *    of g1, g2 = a/N, b/N); then per macro its interior points in block
+ *    order.
+ *  - Vectors are device pointers owned by the caller (float64 for TS_F64,
+ *    float32 for TS_F32 and TS_F16W).  Library objects own their device
+ *    memory and free it in *_destroy.  Work is enqueued on the given HIP
+ *    stream (NULL: the default stream) and is asynchronous unless stated.
+ *  - Every call returns TS_OK or an error code; ts_last_error() describes the
+ *    last failure of the calling thread.  No C++ exception crosses the ABI.
+ */
+#ifndef TWOSCALE_H
+#define TWOSCALE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ts_mesh ts_mesh;
+typedef struct ts_op ts_op;
+typedef struct ts_solver ts_solver;
+typedef void *ts_stream; /* hipStream_t */
+
+enum {
+    TS_OK = 0,
+    TS_EINVAL = 1,     /* bad argument */
+    TS_ENOMEM = 2,     /* device allocation failed or exceeds a budget */
+    TS_EHIP = 3,       /* HIP runtime error */
+    TS_ENOCONV = 4,    /* solver did not reach the tolerance (info filled) */
+    TS_ENONFINITE = 5  /* NaN or Inf in an input or an iterate */
+};
+
+enum { TS_GEOM_SHELL = 0, TS_GEOM_AFFINE = 1 };
+enum { TS_IFEM = 0, TS_LSQP = 1, TS_IPOLY = 2 };
+enum { TS_CENTER_POLY = 0, TS_CENTER_ROWSUM = 1 };
+enum { TS_F64 = 0, TS_F32 = 1, TS_F16W = 2 };
+enum { TS_RHS_MANUFACTURED = 0, TS_RHS_BUMPS = 1, TS_RHS_ONE = 2 };
+
+typedef struct {
+    int level;
+    int N;
+    int64_t n_macros;
+    int64_t block_size;   /* B */
+    int64_t vec_len;      /* n_macros * B */
+    int64_t n_unique;     /* unique nodes incl. Dirichlet */
+    int64_t n_free;       /* unknowns */
+    int64_t n_volume;     /* interior (volume-primitive) nodes */
+} ts_layout_info;
+
+typedef struct {
+    int method;   /* TS_LSQP, TS_IPOLY or TS_IFEM (exact on-the-fly assembly) */
+    int q;        /* surrogate degree 1..4 (IPOLY: 2) */
+    int sample_j; /* LSQP sampling set M_{m(l,j)}, m = min(l, max(1, j)) */
+    int center;   /* TS_CENTER_POLY or TS_CENTER_ROWSUM */
+} ts_op_params;
+
+typedef struct {
+    int nu1, nu2;        /* V(nu1, nu2), default 3, 3 */
+    int max_cycles;      /* cap on outer iterations */
+    int precision;       /* TS_F64, TS_F32 (FP32 cycles + FP64 refinement) or
+                            TS_F16W (FP16 weight evaluation + refinement) */
+    double rtol;         /* stop when ||f - L u||_2 <= rtol ||f||_2 (free rows) */
+    int diverge_window;  /* stop with TS_ENOCONV after this many consecutive
+                            residual increases (0: default 3) */
+} ts_solve_params;
+
+#define TS_MAX_HIST 256
+typedef struct {
+    int cycles;          /* outer iterations done */
+    int status;          /* TS_OK, TS_ENOCONV or TS_ENONFINITE */
+    double rel_residual; /* final ||f - L u|| / ||f|| in FP64 */
+    int n_hist;
+    double hist[TS_MAX_HIST]; /* relative residual before each iteration and at the end */
+} ts_solve_info;
+
+const char *ts_last_error(void);
+
+/* ---- mesh (Sec. 2.2: macro mesh T_-2, blending map Phi) -----------------
+ * vtx: nv x 3 host doubles; tet: nt x 4 host int64 vertex ids (copied).  The
+ * vertex order of each macro is its (i, j, k) frame.  geom: TS_GEOM_SHELL
+ * maps every fine node radially, x = rho(y) y/|y| with y the affine point and
+ * rho the barycentric blend of the vertex radii (nodes of interior macros
+ * form spherical layers); TS_GEOM_AFFINE keeps x = y (Phi = Id).  Fails with
+ * TS_EINVAL if a face is shared by more than two macros, an id is out of
+ * range or a macro is degenerate. */
+int ts_mesh_create(const double *vtx, int64_t nv, const int64_t *tet, int64_t nt, int geom,
+                   ts_mesh **out);
+int ts_mesh_destroy(ts_mesh *mesh);
+int ts_layout(ts_mesh *mesh, int level, ts_layout_info *out);
+
+/* canonical <-> block conversions of float64 device vectors.  to_block zeroes
+ * Dirichlet slots; to_canon reads the first copy of every node. */
+int ts_canon_to_block(ts_mesh *mesh, int level, const double *canon, double *block,
+                      ts_stream s);
+int ts_block_to_canon(ts_mesh *mesh, int level, const double *block, double *canon,
+                      ts_stream s);
+/* blended coordinates of every block slot: xyz is 3 * vec_len doubles
+ * (slot-major, x y z). */
+int ts_node_coords(ts_mesh *mesh, int level, double *xyz, ts_stream s);
+
+/* Load vector f_l = M_l I_l f (Sec. 2.2 eq. algebraic with the consistent P1
+ * mass matrix of the mapped fine tetrahedra applied to the nodal
+ * interpolant of f), float64 block vector, Dirichlet slots 0.
+ *   TS_RHS_MANUFACTURED: f = -Laplace(sin(pi (r - r1)/(r2 - r1)) x y z),
+ *       params = {r1, r2};
+ *   TS_RHS_BUMPS: sum of Gaussians a exp(-|x - c|^2 / (2 s^2)), params =
+ *       records (cx, cy, cz, s, a);
+ *   TS_RHS_ONE: f = 1. */
+int ts_rhs(ts_mesh *mesh, int level, int kind, const double *params, int nparams, double *f,
+           ts_stream s);
+
+/* ---- operator (Sec. 3: IPOLY / LSQP surrogate; Sec. 2.3: IFEM) ----------
+ * Builds the surrogate coefficients of every macro on levels 3..max_level on
+ * the device: exact stencils at the sampling points (Sec. 3.1 for IPOLY, eq.
+ * samplingSetFunctions for LSQP), then the FP64 normal equations
+ * (A^T A) a = A^T b with one Cholesky factor per level (the matrix A is the
+ * same for all macros).  Basis: monomials xi^l eta^m zeta^n with
+ * xi = i/N - 1/4 (same for j, k), degree <= q, ordered by degree, then l
+ * descending, then m descending.  The mesh must outlive the operator. */
+int ts_op_create(ts_mesh *mesh, int max_level, const ts_op_params *p, ts_stream s,
+                 ts_op **out);
+int ts_op_destroy(ts_op *op);
+/* coefficients of one level: n_macros x 15 x m_q host doubles (stencil
+ * direction order mc mw me ms mn mse mnw bc be bn bnw tc tw ts tse);
+ * synchronous.  Import replaces them (checkpoint / shared coefficients). */
+int ts_op_coeffs_export(ts_op *op, int level, double *host, size_t n);
+int ts_op_coeffs_import(ts_op *op, int level, const double *host, size_t n);
+
+/* y = L x (Sec. 3.4 eq. ts): volume rows from the surrogate (IFEM rows for a
+ * TS_IFEM operator or on level 2), lower-primitive rows by element-wise
+ * assembly over all adjacent macros; Dirichlet rows 0. */
+int ts_apply(ts_op *op, int level, int dtype, const void *x, void *y, ts_stream s);
+/* the volume rows only (interior nodes of every macro); other slots of y
+ * are left untouched */
+int ts_apply_volume(ts_op *op, int level, int dtype, const void *x, void *y, ts_stream s);
+/* r = f - L u */
+int ts_residual(ts_op *op, int level, int dtype, const void *f, const void *u, void *r,
+                ts_stream s);
+/* multicolour Gauss-Seidel (eq. iteration-scheme), in place: per sweep the
+ * phases vertices; edge points by a mod 2; face points by (a + 2b) mod 3;
+ * volume points by (i + 2j + 3k) mod 4.  Inside a phase every point is
+ * updated from the values at the start of the phase. */
+int ts_smooth(ts_op *op, int level, int dtype, const void *f, void *u, int sweeps,
+              ts_stream s);
+/* grid transfer between level and level - 1: linear interpolation in index
+ * space P and its transpose R = P^T (Dirichlet rows 0). */
+int ts_restrict(ts_op *op, int level, int dtype, const void *rf, void *rc, ts_stream s);
+int ts_prolongate_add(ts_op *op, int level, int dtype, const void *uc, void *uf, ts_stream s);
+/* sqrt(sum over free nodes of x^2), each node once; synchronous,
+ * deterministic (fixed reduction order). */
+int ts_norm2(ts_mesh *mesh, int level, int dtype, const void *x, double *out, ts_stream s);
+
+/* ---- multigrid (Sec. 4.1: V(3,3) with Gauss-Seidel smoothing) -----------
+ * Coarsest level 2 is solved exactly in FP64 with the inverse of its IFEM
+ * matrix (computed on the device at creation).  Workspace owned by the
+ * solver. */
+int ts_solver_create(ts_op *op, int level, const ts_solve_params *p, ts_solver **out);
+int ts_solver_destroy(ts_solver *sv);
+/* one V(nu1, nu2) cycle on L u = f at the solver's level, in place */
+int ts_vcycle(ts_solver *sv, int dtype, const void *f, void *u, ts_stream s);
+/* full solve: u (float64, initial guess on entry) until the FP64 relative
+ * residual <= rtol.  TS_F32 / TS_F16W precision: FP64 residual, FP32 V-cycle
+ * on the correction, FP64 update (iterative refinement).  Synchronous once
+ * per iteration (residual norm).  Returns TS_ENOCONV / TS_ENONFINITE with
+ * info filled when it stops early. */
+int ts_solve(ts_solver *sv, const double *f, double *u, ts_solve_info *info, ts_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TWOSCALE_H */

@@ -1,0 +1,722 @@
+// Kernels around the stencils: grid transfer (linear interpolation in
+// index space and its transpose), deterministic norms, element-wise vector
+// work, canonical <-> block conversion, node coordinates, load vectors with
+// the consistent P1 mass matrix, the surrogate setup (exact stencils at the
+// sampling points and the FP64 normal equations, Sec. 3.1-3.2) and the
+// coarsest-level dense inverse (Gauss-Jordan) with its solve.
+#include <math.h>
+
+#include "ts_internal.h"
+
+namespace ts {
+
+// ---------------------------------------------------------------- helpers
+
+// slot (position r in plane k) -> (i, j): row j has A - j slots, A = N+1-k
+__device__ __forceinline__ void plane_pos_to_ij(int r, int A, int& i, int& j) {
+    const double a = 2.0 * A + 1.0;
+    int J = (int)((a - sqrt(a * a - 8.0 * r)) * 0.5);
+    if (J < 0) J = 0;
+    while (J > 0 && J * (2 * A - J + 1) / 2 > r) J--;
+    while ((J + 1) * (2 * A - J) / 2 <= r) J++;
+    j = J;
+    i = r - J * (2 * A - J + 1) / 2;
+}
+
+// all-slot kernels: grid = n_macros x n_slot_tiles (tiles of plane k)
+#define TS_SLOT_DECODE(L_ARGS)                                                       \
+    const int macro = blockIdx.y;                                                    \
+    const int2 td = slot_tiles[blockIdx.x];                                          \
+    const int k = td.x;                                                              \
+    const int A = N + 1 - k;                                                         \
+    const int r = td.y + (int)threadIdx.x;                                           \
+    if (r >= A * (A + 1) / 2) return;                                                \
+    int i, j;                                                                        \
+    plane_pos_to_ij(r, A, i, j);                                                     \
+    const size_t slot = (size_t)macro * B + plane_off(N, k) + r;
+
+// ---------------------------------------------------------------- transfers
+
+// coarse interior nodes: r_c = r_f(2c) + 1/2 sum_w r_f(2c + w) (R = P^T;
+// every fine midpoint around an interior coarse node is interior to the
+// macro)
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_volume(
+    const T* __restrict__ rf, T* __restrict__ rc, const int2* __restrict__ slot_tiles, int Nc,
+    int64_t Bf, int64_t Bc) {
+    const int N = Nc;
+    const int64_t B = Bc;
+    TS_SLOT_DECODE();
+    if (i < 1 || j < 1 || k < 1 || i + j + k > Nc - 1) return;
+    const int Nf = 2 * Nc;
+    const T* fm = rf + (size_t)macro * Bf;
+    T s = fm[bidx(Nf, 2 * i, 2 * j, 2 * k)];
+    T h = (T)0;
+#pragma unroll
+    for (int w = 1; w < NW; w++) h += fm[bidx(Nf, 2 * i + dir_i(w), 2 * j + dir_j(w), 2 * k + dir_k(w))];
+    rc[slot] = s + (T)0.5 * h;
+}
+
+// number of macros containing the primitive of fine node p in macro t
+__device__ __forceinline__ int node_mult(const MacroTopo& T, int N, int i, int j, int k) {
+    const int mu[4] = {N - i - j - k, i, j, k};
+    int z[4], nz = 0;
+    for (int a = 0; a < 4; a++)
+        if (mu[a] == 0) z[nz++] = a;
+    if (nz == 0) return 1;
+    if (nz == 1) return T.fmult[z[0]];
+    // edge: the two local vertices that are not zero
+    int a = -1, b = -1;
+    for (int q = 0; q < 4; q++)
+        if (mu[q] != 0) {
+            if (a < 0) a = q; else b = q;
+        }
+    const int EL[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    for (int e = 0; e < 6; e++)
+        if (EL[e][0] == a && EL[e][1] == b) return T.emult[e];
+    return 1;
+}
+
+// coarse lower-primitive nodes: sum over the node's copies of the fine
+// midpoints in that macro, each divided by the number of macros that hold it
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_iface(
+    const T* __restrict__ rf, T* __restrict__ rc, const int* __restrict__ off,
+    const int4* __restrict__ cp, const unsigned char* __restrict__ flag, int n,
+    const MacroTopo* __restrict__ topo, int Nc, int64_t Bf, int64_t Bc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int c0 = off[t], c1 = off[t + 1];
+    double v = 0.0;
+    if (!(flag[t] & 1)) {
+        const int Nf = 2 * Nc;
+        const int4 q0 = cp[c0];
+        v = (double)rf[(size_t)q0.x * Bf + bidx(Nf, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
+        for (int c = c0; c < c1; c++) {
+            const int4 q = cp[c];
+            const MacroTopo& TP = topo[q.x];
+            const T* fm = rf + (size_t)q.x * Bf;
+            for (int w = 1; w < NW; w++) {
+                if (!inside(Nc, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w))) continue;
+                const int a = 2 * q.y + dir_i(w), b = 2 * q.z + dir_j(w), cc = 2 * q.w + dir_k(w);
+                v += 0.5 * (double)fm[bidx(Nf, a, b, cc)] / (double)node_mult(TP, Nf, a, b, cc);
+            }
+        }
+    }
+    for (int c = c0; c < c1; c++) {
+        const int4 q = cp[c];
+        rc[(size_t)q.x * Bc + bidx(Nc, q.y, q.z, q.w)] = (T)v;
+    }
+}
+
+// u_f += P u_c over every fine slot: even nodes copy the coarse node, odd
+// nodes average the two ends of the coarse edge they bisect
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolongate_add(
+    const T* __restrict__ uc, T* __restrict__ uf, const int2* __restrict__ slot_tiles, int N,
+    int64_t B, int64_t Bc) {
+    TS_SLOT_DECODE();
+    const int Nc = N / 2;
+    const T* cm = uc + (size_t)macro * Bc;
+    const int pi = i & 1, pj = j & 1, pk = k & 1;
+    T v;
+    if (!(pi | pj | pk)) {
+        v = cm[bidx(Nc, i / 2, j / 2, k / 2)];
+    } else {
+        // the lattice edge direction with this parity pattern
+        int di, dj, dk;
+        if (pi && !pj && !pk) { di = 1; dj = 0; dk = 0; }
+        else if (!pi && pj && !pk) { di = 0; dj = 1; dk = 0; }
+        else if (!pi && !pj && pk) { di = 0; dj = 0; dk = 1; }
+        else if (pi && pj && !pk) { di = 1; dj = -1; dk = 0; }
+        else if (pi && !pj && pk) { di = -1; dj = 0; dk = 1; }
+        else if (!pi && pj && pk) { di = 0; dj = -1; dk = 1; }
+        else { di = 1; dj = -1; dk = 1; }
+        const T a = cm[bidx(Nc, (i - di) / 2, (j - dj) / 2, (k - dk) / 2)];
+        const T b = cm[bidx(Nc, (i + di) / 2, (j + dj) / 2, (k + dk) / 2)];
+        v = (T)0.5 * (a + b);
+    }
+    uf[slot] += v;
+}
+
+void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* rc,
+                     hipStream_t s) {
+    Mesh& MM = const_cast<Mesh&>(M);
+    const Level& Lf = MM.level(lam_f);
+    const Level& Lc = MM.level(lam_f - 1);
+    const dim3 g1(Lc.n_slot_tiles, (unsigned)M.nt), b1(256);
+    const dim3 g2((unsigned)((Lc.n_if + 255) / 256)), b2(256);
+    if (dtype == TS_F64) {
+        k_restrict_volume<double><<<g1, b1, 0, s>>>((const double*)rf, (double*)rc, Lc.slot_tiles.p, Lc.N, Lf.B, Lc.B);
+        k_restrict_iface<double><<<g2, b2, 0, s>>>((const double*)rf, (double*)rc, Lc.if_off.p, Lc.if_copy.p, Lc.if_flag.p, (int)Lc.n_if, M.d_topo.p, Lc.N, Lf.B, Lc.B);
+    } else {
+        k_restrict_volume<float><<<g1, b1, 0, s>>>((const float*)rf, (float*)rc, Lc.slot_tiles.p, Lc.N, Lf.B, Lc.B);
+        k_restrict_iface<float><<<g2, b2, 0, s>>>((const float*)rf, (float*)rc, Lc.if_off.p, Lc.if_copy.p, Lc.if_flag.p, (int)Lc.n_if, M.d_topo.p, Lc.N, Lf.B, Lc.B);
+    }
+    TS_HIP(hipGetLastError());
+}
+
+void launch_prolongate_add(const Mesh& M, int lam_f, int dtype, const void* uc, void* uf,
+                           hipStream_t s) {
+    Mesh& MM = const_cast<Mesh&>(M);
+    const Level& Lf = MM.level(lam_f);
+    const Level& Lc = MM.level(lam_f - 1);
+    const dim3 g(Lf.n_slot_tiles, (unsigned)M.nt), b(256);
+    if (dtype == TS_F64)
+        k_prolongate_add<double><<<g, b, 0, s>>>((const double*)uc, (double*)uf, Lf.slot_tiles.p, Lf.N, Lf.B, Lc.B);
+    else
+        k_prolongate_add<float><<<g, b, 0, s>>>((const float*)uc, (float*)uf, Lf.slot_tiles.p, Lf.N, Lf.B, Lc.B);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- vectors
+
+template <typename T>
+__global__ void k_fill(T* x, int64_t n, T v) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        x[t] = v;
+}
+template <typename S, typename D>
+__global__ void k_cast(const S* __restrict__ a, D* __restrict__ b, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        b[t] = (D)a[t];
+}
+template <typename S>
+__global__ void k_axpy(double a, const S* __restrict__ x, double* __restrict__ y, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        y[t] += a * (double)x[t];
+}
+
+static dim3 ew_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+void launch_fill(void* x, int dtype, int64_t n, double v, hipStream_t s) {
+    if (dtype == TS_F64)
+        k_fill<double><<<ew_grid(n), 256, 0, s>>>((double*)x, n, v);
+    else
+        k_fill<float><<<ew_grid(n), 256, 0, s>>>((float*)x, n, (float)v);
+    TS_HIP(hipGetLastError());
+}
+void launch_cast(const void* src, int dsrc, void* dst, int ddst, int64_t n, hipStream_t s) {
+    const bool s64 = dsrc == TS_F64, d64 = ddst == TS_F64;
+    if (s64 && !d64) k_cast<double, float><<<ew_grid(n), 256, 0, s>>>((const double*)src, (float*)dst, n);
+    else if (!s64 && d64) k_cast<float, double><<<ew_grid(n), 256, 0, s>>>((const float*)src, (double*)dst, n);
+    else if (s64) k_cast<double, double><<<ew_grid(n), 256, 0, s>>>((const double*)src, (double*)dst, n);
+    else k_cast<float, float><<<ew_grid(n), 256, 0, s>>>((const float*)src, (float*)dst, n);
+    TS_HIP(hipGetLastError());
+}
+void launch_axpy(double a, const void* x, int dx, double* y, int64_t n, hipStream_t s) {
+    if (dx == TS_F64)
+        k_axpy<double><<<ew_grid(n), 256, 0, s>>>(a, (const double*)x, y, n);
+    else
+        k_axpy<float><<<ew_grid(n), 256, 0, s>>>(a, (const float*)x, y, n);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- norms
+// Deterministic: fixed per-block tree sums into partial[], then one block
+// sums partial[] in a fixed order.
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x, const int2* __restrict__ slot_tiles,
+                                                     int N, int64_t B, double* __restrict__ partial) {
+    const int macro = blockIdx.y;
+    const int2 td = slot_tiles[blockIdx.x];
+    const int k = td.x;
+    const int A = N + 1 - k;
+    const int r = td.y + (int)threadIdx.x;
+    double v = 0.0;
+    if (r < A * (A + 1) / 2) {
+        int i, j;
+        plane_pos_to_ij(r, A, i, j);
+        if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= N - 1) {
+            const double a = (double)x[(size_t)macro * B + plane_off(N, k) + r];
+            v = a * a;
+        }
+    }
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm_iface(const T* __restrict__ x, const int* __restrict__ list,
+                                                    int n, const int* __restrict__ off,
+                                                    const int4* __restrict__ cp, int N, int64_t B,
+                                                    double* __restrict__ partial) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (t < n) {
+        const int4 q = cp[off[list[t]]];
+        const double a = (double)x[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)];
+        v = a * a;
+    }
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int64_t n, double* out) {
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += 256) v += p[t];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+int64_t norm_partial_count(const Mesh& M, int lam) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    return (int64_t)L.n_slot_tiles * M.nt + (L.n_if_free + 255) / 256 + 1;
+}
+
+void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
+                       double* out, hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    const dim3 g1(L.n_slot_tiles, (unsigned)M.nt);
+    const int64_t n1 = (int64_t)L.n_slot_tiles * M.nt;
+    const int n2 = (L.n_if_free + 255) / 256;
+    if (dtype == TS_F64) {
+        k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.slot_tiles.p, L.N, L.B, partial);
+        if (n2) k_norm_iface<double><<<n2, 256, 0, s>>>((const double*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
+    } else {
+        k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.slot_tiles.p, L.N, L.B, partial);
+        if (n2) k_norm_iface<float><<<n2, 256, 0, s>>>((const float*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
+    }
+    k_sum_partials<<<1, 256, 0, s>>>(partial, n1 + n2, out);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- canonical
+
+__device__ __forceinline__ int64_t canon_of(const MacroTopo& T, int64_t m, int N, int64_t nv,
+                                            int64_t ne, int64_t nf, int i, int j, int k,
+                                            int* dir) {
+    const int mu[4] = {N - i - j - k, i, j, k};
+    int nz = 0, zero_at = -1;
+    for (int a = 0; a < 4; a++) {
+        if (mu[a] != 0) nz++;
+        else zero_at = a;
+    }
+    const int64_t F = (int64_t)(N - 1) * (N - 2) / 2;
+    if (nz == 1) {
+        for (int a = 0; a < 4; a++)
+            if (mu[a] == N) {
+                *dir = T.vdir[a];
+                return T.vg[a];
+            }
+    }
+    if (nz == 2) {
+        for (int e = 0; e < 6; e++)
+            if (mu[T.elo[e]] != 0 && mu[T.ehi[e]] != 0) {
+                *dir = T.edir[e];
+                return nv + T.e[e] * (N - 1) + (mu[T.ehi[e]] - 1);
+            }
+    }
+    if (nz == 3) {
+        const int o = zero_at;
+        const int a = mu[T.fs[o][1]], b = mu[T.fs[o][2]];
+        *dir = T.fdir[o];
+        const int64_t fo = (int64_t)(b - 1) * (N - 1) - (int64_t)(b - 1) * b / 2 + (a - 1);
+        return nv + ne * (N - 1) + T.f[o] * F + fo;
+    }
+    *dir = 0;
+    const int64_t V = (int64_t)(N - 1) * (N - 2) * (N - 3) / 6;
+    const int64_t vo = tet_n(N - 3) - tet_n(N - 2 - k) + (int64_t)(j - 1) * (N - 1 - k) -
+                       (int64_t)(j - 1) * j / 2 + (i - 1);
+    return nv + ne * (N - 1) + nf * F + m * V + vo;
+}
+
+__global__ __launch_bounds__(256) void k_canon_to_block(const double* __restrict__ c, double* __restrict__ b,
+                                                        const MacroTopo* __restrict__ topo,
+                                                        const int2* __restrict__ slot_tiles, int N,
+                                                        int64_t B, int64_t nv, int64_t ne, int64_t nf) {
+    TS_SLOT_DECODE();
+    int dir;
+    const int64_t id = canon_of(topo[macro], macro, N, nv, ne, nf, i, j, k, &dir);
+    b[slot] = dir ? 0.0 : c[id];
+}
+
+__global__ __launch_bounds__(256) void k_block_to_canon(const double* __restrict__ b, double* __restrict__ c,
+                                                        const MacroTopo* __restrict__ topo,
+                                                        const int2* __restrict__ slot_tiles, int N,
+                                                        int64_t B, int64_t nv, int64_t ne, int64_t nf,
+                                                        const int* __restrict__ off,
+                                                        const int4* __restrict__ cp) {
+    TS_SLOT_DECODE();
+    int dir;
+    const int64_t id = canon_of(topo[macro], macro, N, nv, ne, nf, i, j, k, &dir);
+    const bool interior = i >= 1 && j >= 1 && k >= 1 && i + j + k <= N - 1;
+    if (interior) {
+        c[id] = b[slot];
+    } else {
+        // only the first copy writes
+        const int4 q = cp[off[id]];
+        if (q.x == macro && q.y == i && q.z == j && q.w == k) c[id] = b[slot];
+    }
+}
+
+void launch_canon_to_block(const Mesh& M, int lam, const double* c, double* b, hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    const dim3 g(L.n_slot_tiles, (unsigned)M.nt);
+    k_canon_to_block<<<g, 256, 0, s>>>(c, b, M.d_topo.p, L.slot_tiles.p, L.N, L.B, M.nv, M.ne, M.nf);
+    TS_HIP(hipGetLastError());
+}
+void launch_block_to_canon(const Mesh& M, int lam, const double* b, double* c, hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    const dim3 g(L.n_slot_tiles, (unsigned)M.nt);
+    k_block_to_canon<<<g, 256, 0, s>>>(b, c, M.d_topo.p, L.slot_tiles.p, L.N, L.B, M.nv, M.ne, M.nf, L.if_off.p, L.if_copy.p);
+    TS_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_coords(double* __restrict__ xyz, const MacroGeom* __restrict__ geom,
+                                                const int2* __restrict__ slot_tiles, int N, int64_t B) {
+    TS_SLOT_DECODE();
+    double x[3];
+    node_xyz(geom[macro], N, i, j, k, x);
+    xyz[3 * slot] = x[0];
+    xyz[3 * slot + 1] = x[1];
+    xyz[3 * slot + 2] = x[2];
+}
+
+void launch_coords(const Mesh& M, int lam, double* xyz, hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    const dim3 g(L.n_slot_tiles, (unsigned)M.nt);
+    k_coords<<<g, 256, 0, s>>>(xyz, M.d_geom.p, L.slot_tiles.p, L.N, L.B);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- load vector
+
+__device__ __forceinline__ double rhs_point(int kind, const double* par, int np, const double* x) {
+    if (kind == TS_RHS_MANUFACTURED) {
+        const double r1 = par[0], r2 = par[1], d = r2 - r1;
+        const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        const double kk = M_PI / d;
+        const double th = kk * (r - r1);
+        const double h = x[0] * x[1] * x[2];
+        return h * (kk * kk * sin(th) - (8.0 / r) * kk * cos(th));
+    }
+    if (kind == TS_RHS_BUMPS) {
+        double s = 0.0;
+        for (int b = 0; b + 5 <= np; b += 5) {
+            const double dx = x[0] - par[b], dy = x[1] - par[b + 1], dz = x[2] - par[b + 2];
+            const double sg = par[b + 3];
+            s += par[b + 4] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * sg * sg));
+        }
+        return s;
+    }
+    return 1.0;
+}
+
+// partial consistent-mass row of local node (i,j,k) of one macro applied to
+// the nodal values of f: sum_T |T|/20 (2 f_I + sum_{J in T, J != I} f_J)
+__device__ double mass_partial(const MacroGeom& g, int N, int i, int j, int k,
+                               int kind, const double* par, int np) {
+    double xs[NW][3], fv[NW];
+    unsigned valid = 0;
+    for (int w = 0; w < NW; w++) {
+        const int a = i + dir_i(w), b = j + dir_j(w), c = k + dir_k(w);
+        if (inside(N, a, b, c)) {
+            valid |= 1u << w;
+            node_xyz(g, N, a, b, c, xs[w]);
+            fv[w] = rhs_point(kind, par, np, xs[w]);
+        }
+    }
+    double s = 0.0;
+    for (int t = 0; t < 24; t++) {
+        const int w0 = kTets24.t[t][0], w1 = kTets24.t[t][1], w2 = kTets24.t[t][2],
+                  w3 = kTets24.t[t][3];
+        const unsigned need = (1u << w0) | (1u << w1) | (1u << w2) | (1u << w3);
+        if ((valid & need) != need) continue;
+        double K[4];
+        const double vol = stiffness_row0(xs[w0], xs[w1], xs[w2], xs[w3], K);
+        s += vol / 20.0 * (2.0 * fv[w0] + fv[w1] + fv[w2] + fv[w3]);
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_rhs_volume(double* __restrict__ f, const MacroGeom* __restrict__ geom,
+                                                    const int2* __restrict__ slot_tiles,
+                                                    int N, int64_t B, int kind,
+                                                    const double* __restrict__ par, int np) {
+    TS_SLOT_DECODE();
+    if (i < 1 || j < 1 || k < 1 || i + j + k > N - 1) return;
+    f[slot] = mass_partial(geom[macro], N, i, j, k, kind, par, np);
+}
+
+__global__ __launch_bounds__(256) void k_rhs_iface(double* __restrict__ f, const MacroGeom* __restrict__ geom,
+                                                   const int* __restrict__ off,
+                                                   const int4* __restrict__ cp,
+                                                   const unsigned char* __restrict__ flag, int n, int N,
+                                                   int64_t B, int kind, const double* __restrict__ par,
+                                                   int np) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double v = 0.0;
+    if (!(flag[t] & 1))
+        for (int c = off[t]; c < off[t + 1]; c++) {
+            const int4 q = cp[c];
+            v += mass_partial(geom[q.x], N, q.y, q.z, q.w, kind, par, np);
+        }
+    for (int c = off[t]; c < off[t + 1]; c++) {
+        const int4 q = cp[c];
+        f[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = v;
+    }
+}
+
+void launch_rhs(const Mesh& M, int lam, int kind, const double* dpar, int npar, double* f,
+                hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    const dim3 g(L.n_slot_tiles, (unsigned)M.nt);
+    k_rhs_volume<<<g, 256, 0, s>>>(f, M.d_geom.p, L.slot_tiles.p, L.N, L.B, kind, dpar, npar);
+    const int n = (int)L.n_if;
+    if (n) k_rhs_iface<<<(n + 255) / 256, 256, 0, s>>>(f, M.d_geom.p, L.if_off.p, L.if_copy.p, L.if_flag.p, n, L.N, L.B, kind, dpar, npar);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- setup
+
+// exact (IFEM) stencils at the sampling points of every macro: B[m][s][15]
+__global__ __launch_bounds__(128) void k_sample(double* __restrict__ Bout, const MacroGeom* __restrict__ geom,
+                                                const int* __restrict__ pts, int npts, int N) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (s >= npts) return;
+    double st[NW];
+    ifem_partial_stencil(geom[m], N, pts[3 * s], pts[3 * s + 1], pts[3 * s + 2], st);
+    double* o = Bout + ((size_t)m * npts + s) * NW;
+    for (int w = 0; w < NW; w++) o[w] = st[w];
+}
+
+void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s) {
+    const dim3 g((npts + 127) / 128, (unsigned)M.nt);
+    k_sample<<<g, 128, 0, s>>>(B, M.d_geom.p, pts, npts, 1 << lam);
+    TS_HIP(hipGetLastError());
+}
+
+// monomial basis of the centred, scaled coordinates (degree, then l, then m
+// descending)
+__device__ __forceinline__ int basis_row(int q, int N, int i, int j, int k, double* row) {
+    const double xi = (double)i / N - 0.25, eta = (double)j / N - 0.25, ze = (double)k / N - 0.25;
+    int c = 0;
+    for (int d = 0; d <= q; d++)
+        for (int l = d; l >= 0; l--)
+            for (int m = d - l; m >= 0; m--) {
+                const int n = d - l - m;
+                double v = 1.0;
+                for (int a = 0; a < l; a++) v *= xi;
+                for (int a = 0; a < m; a++) v *= eta;
+                for (int a = 0; a < n; a++) v *= ze;
+                row[c++] = v;
+            }
+    return c;
+}
+
+// G = A^T A and its Cholesky factor (lower, row-major) into work[0..mq*mq)
+__global__ __launch_bounds__(256) void k_fit_gram(int N, int q, const int* __restrict__ pts, int npts,
+                                                  double* __restrict__ work) {
+    __shared__ double G[35 * 35];
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) {
+        const int a = e / mq, b = e % mq;
+        double s = 0.0;
+        double row[35];
+        for (int p = 0; p < npts; p++) {
+            basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
+            s += row[a] * row[b];
+        }
+        G[e] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int jj = 0; jj < mq; jj++) {
+            double d = G[jj * mq + jj];
+            for (int kk = 0; kk < jj; kk++) d -= G[jj * mq + kk] * G[jj * mq + kk];
+            d = sqrt(d);
+            G[jj * mq + jj] = d;
+            for (int ii = jj + 1; ii < mq; ii++) {
+                double t = G[ii * mq + jj];
+                for (int kk = 0; kk < jj; kk++) t -= G[ii * mq + kk] * G[jj * mq + kk];
+                G[ii * mq + jj] = t / d;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) work[e] = G[e];
+}
+
+// per macro: rhs = A^T B_m, then (L L^T) a = rhs; coef[m][w][c]
+__global__ __launch_bounds__(256) void k_fit_solve(int N, int q, const int* __restrict__ pts, int npts,
+                                                   const double* __restrict__ Bv, const double* __restrict__ Lf,
+                                                   double* __restrict__ coef) {
+    __shared__ double R[35 * NW];
+    const int m = blockIdx.x;
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    const double* Bm = Bv + (size_t)m * npts * NW;
+    for (int e = threadIdx.x; e < mq * NW; e += blockDim.x) {
+        const int c = e / NW, w = e % NW;
+        double s = 0.0;
+        double row[35];
+        for (int p = 0; p < npts; p++) {
+            basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
+            s += row[c] * Bm[(size_t)p * NW + w];
+        }
+        R[c * NW + w] = s;
+    }
+    __syncthreads();
+    const int w = threadIdx.x;
+    if (w < NW) {
+        double z[35];
+        for (int ii = 0; ii < mq; ii++) {
+            double t = R[ii * NW + w];
+            for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
+            z[ii] = t / Lf[ii * mq + ii];
+        }
+        for (int ii = mq - 1; ii >= 0; ii--) {
+            double t = z[ii];
+            for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
+            z[ii] = t / Lf[ii * mq + ii];
+        }
+        for (int c = 0; c < mq; c++) coef[((size_t)m * NW + w) * mq + c] = z[c];
+    }
+}
+
+void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt, double* coef,
+                double* work, hipStream_t s) {
+    k_fit_gram<<<1, 256, 0, s>>>(N, q, pts, npts, work);
+    k_fit_solve<<<nt, 256, 0, s>>>(N, q, pts, npts, B, work, coef);
+    TS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- coarse level
+
+// dense IFEM matrix of the free nodes: thread per free row r with copies
+// cp[off[r] .. off[r+1]); slot_free maps block slots to free indices (-1:
+// Dirichlet)
+__global__ __launch_bounds__(64) void k_dense_assemble(const MacroGeom* __restrict__ geom,
+                                                       const int* __restrict__ off,
+                                                       const int4* __restrict__ cp, int nfree,
+                                                       const int* __restrict__ slot_free, int N,
+                                                       int64_t B, double* __restrict__ A) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nfree) return;
+    double* row = A + (size_t)r * nfree;
+    for (int c = off[r]; c < off[r + 1]; c++) {
+        const int4 q = cp[c];
+        double s[NW];
+        ifem_partial_stencil(geom[q.x], N, q.y, q.z, q.w, s);
+        for (int w = 0; w < NW; w++) {
+            const int a = q.y + dir_i(w), b = q.z + dir_j(w), cc = q.w + dir_k(w);
+            if (!inside(N, a, b, cc)) continue;
+            const int col = slot_free[(size_t)q.x * B + bidx(N, a, b, cc)];
+            if (col >= 0) row[col] += s[w];
+        }
+    }
+}
+
+// Gauss-Jordan step k (no pivoting: the matrix is SPD): save column k,
+// scale row k by 1/A_kk (A_kk <- 1/A_kk) ...
+__global__ __launch_bounds__(256) void k_gj_pivot(double* A, double* col, int n, int k) {
+    const double piv = A[(size_t)k * n + k];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) col[i] = A[(size_t)i * n + k];
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < n; jj += blockDim.x)
+        A[(size_t)k * n + jj] = (jj == k) ? 1.0 / piv : A[(size_t)k * n + jj] / piv;
+}
+// ... then eliminate column k from every other row
+__global__ __launch_bounds__(256) void k_gj_update(double* A, const double* __restrict__ col, int n, int k) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (jj >= n || i == k) return;
+    const double f = col[i];
+    const double a = (jj == k) ? 0.0 : A[(size_t)i * n + jj];
+    A[(size_t)i * n + jj] = a - f * A[(size_t)k * n + jj];
+}
+
+void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s) {
+    k_gj_pivot<<<1, 256, 0, s>>>(A, col, n, k);
+    k_gj_update<<<dim3((n + 255) / 256, n), 256, 0, s>>>(A, col, n, k);
+}
+
+// u = Ainv f on the coarsest level: gather f at the first copy of each free
+// node, dense product (A^-1 stored transposed: coalesced columns), scatter to
+// every copy
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_gather(const T* __restrict__ f, const int* __restrict__ off,
+                                                       const int64_t* __restrict__ slot, int n,
+                                                       double* __restrict__ fb) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) fb[r] = (double)f[slot[off[r]]];
+}
+__global__ __launch_bounds__(256) void k_coarse_matvec(const double* __restrict__ AinvT, const double* __restrict__ fb,
+                                                       int n, double* __restrict__ ub) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < n; c++) s += AinvT[(size_t)c * n + r] * fb[c];
+    ub[r] = s;
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_scatter(T* __restrict__ u, const int* __restrict__ off,
+                                                        const int64_t* __restrict__ slot, int n,
+                                                        const double* __restrict__ ub) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const T v = (T)ub[r];
+    for (int c = off[r]; c < off[r + 1]; c++) u[slot[c]] = v;
+}
+
+void launch_coarse_solve(const double* AinvT, int n, const int* free_first, const int* cp_off,
+                         const int64_t* cp_slot, int dtype, const void* f, void* u,
+                         double* work, hipStream_t s) {
+    (void)free_first;
+    const int g = (n + 255) / 256;
+    double* fb = work;
+    double* ub = work + n;
+    if (dtype == TS_F64) {
+        k_coarse_gather<double><<<g, 256, 0, s>>>((const double*)f, cp_off, cp_slot, n, fb);
+        k_coarse_matvec<<<g, 256, 0, s>>>(AinvT, fb, n, ub);
+        k_coarse_scatter<double><<<g, 256, 0, s>>>((double*)u, cp_off, cp_slot, n, ub);
+    } else {
+        k_coarse_gather<float><<<g, 256, 0, s>>>((const float*)f, cp_off, cp_slot, n, fb);
+        k_coarse_matvec<<<g, 256, 0, s>>>(AinvT, fb, n, ub);
+        k_coarse_scatter<float><<<g, 256, 0, s>>>((float*)u, cp_off, cp_slot, n, ub);
+    }
+    TS_HIP(hipGetLastError());
+}
+
+// exported for the solver: dense assembly with explicit copies
+void launch_dense_assemble_cp(const Mesh& M, int lam, const int* off, const int4* cp, int nfree,
+                              const int* slot_free, double* A, hipStream_t s) {
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    k_dense_assemble<<<(nfree + 63) / 64, 64, 0, s>>>(M.d_geom.p, off, cp, nfree, slot_free, L.N, L.B, A);
+    TS_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_transpose(const T* __restrict__ a, T* __restrict__ b, int n) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c < n) b[(size_t)c * n + r] = a[(size_t)r * n + c];
+}
+void launch_transpose(const double* a, double* b, int n, hipStream_t s) {
+    k_transpose<double><<<dim3((n + 255) / 256, n), 256, 0, s>>>(a, b, n);
+    TS_HIP(hipGetLastError());
+}
+
+}  // namespace ts

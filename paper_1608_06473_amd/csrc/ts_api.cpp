@@ -1,0 +1,633 @@
+// C ABI of the two-scale library: host orchestration of the kernels.
+// Setup of the surrogate (Sec. 3.1-3.3), operator application and smoothing
+// (Sec. 3.4, eq. iteration-scheme), V(nu1, nu2) multigrid (Sec. 4.1) with an
+// exact FP64 coarsest level, and the FP64 / mixed-precision solve.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+#include "ts_internal.h"
+
+namespace ts {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+template <class F>
+static int guarded(F&& f) {
+    try {
+        f();
+        return TS_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return TS_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return TS_EINVAL;
+    }
+}
+
+static hipStream_t S(ts_stream s) { return (hipStream_t)s; }
+
+static int mq_of(int q) { return (q + 1) * (q + 2) * (q + 3) / 6; }
+
+// Sampling points of a level (N intervals): LSQP uses the interior nodes of
+// the level-m lattice, m = min(l, max(1, j)) with l = log2(N) - 2, embedded
+// at stride N / 2^(m+2) (eq. samplingSetFunctions); IPOLY the ten quadratic
+// nodes of the shrunk macro, a = N - 3, b = N/2 - 1 (Sec. 3.1).
+static std::vector<int> sample_points(int N, int method, int jsamp) {
+    std::vector<int> p;
+    if (method == TS_IPOLY) {
+        const int a = N - 3, b = N / 2 - 1;
+        const int P[10][3] = {{1, 1, 1}, {1, 1, a}, {1, a, 1}, {a, 1, 1}, {1, 1, b},
+                              {1, b, 1}, {b, 1, 1}, {1, b, b}, {b, 1, b}, {b, b, 1}};
+        for (auto& r : P) p.insert(p.end(), r, r + 3);
+        return p;
+    }
+    int l = 0;
+    while ((4 << l) < N) l++;
+    int m = std::min(l, std::max(1, jsamp));
+    const int Ns = 4 << m, st = N / Ns;
+    for (int k = 1; k <= Ns - 3; k++)
+        for (int j = 1; j <= Ns - 2 - k; j++)
+            for (int i = 1; i <= Ns - 1 - j - k; i++) {
+                p.push_back(i * st);
+                p.push_back(j * st);
+                p.push_back(k * st);
+            }
+    return p;
+}
+
+static bool uses_surrogate(const ts_op* op, int lam) {
+    return op->p.method != TS_IFEM && lam >= 3 && op->lv.count(lam) && op->lv.at(lam)->has_coef;
+}
+
+static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vector<double>& h) {
+    const int N = 1 << lam;
+    std::vector<float> f32(h.size()), f16s(h.size());
+    for (size_t i = 0; i < h.size(); i++) {
+        f32[i] = (float)h[i];
+        f16s[i] = (float)(h[i] * N);
+    }
+    lo.coef32.upload(f32);
+    lo.coef16s.upload(f16s);
+    lo.has_coef = true;
+    (void)op;
+}
+
+static void setup_level(ts_op* op, int lam, hipStream_t s) {
+    Mesh& M = op->mesh->m;
+    auto lo = std::make_unique<LevelOp>();
+    lo->lam = lam;
+    M.level(lam);
+    if (op->p.method != TS_IFEM && lam >= 3) {
+        const int N = 1 << lam, q = op->p.q, mq = op->mq;
+        std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
+        const int np = (int)pts.size() / 3;
+        TS_REQUIRE(np >= mq, TS_EINVAL, "sampling set smaller than the polynomial space");
+        DBuf<int> dp;
+        dp.upload(pts);
+        DBuf<double> Bv, work;
+        Bv.alloc((size_t)M.nt * np * NW);
+        work.alloc((size_t)mq * mq);
+        lo->coef64.alloc((size_t)M.nt * NW * mq);
+        launch_sample(M, lam, dp.p, np, Bv.p, s);
+        launch_fit(N, q, dp.p, np, Bv.p, (int)M.nt, lo->coef64.p, work.p, s);
+        std::vector<double> h((size_t)M.nt * NW * mq);
+        TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+        for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite surrogate coefficient");
+        upload_coef_variants(op, *lo, lam, h);
+    }
+    op->lv[lam] = std::move(lo);
+}
+
+// Scratch buffers owned by the operator (per level): interface GS values.
+struct OpScratch {
+    std::map<int, std::unique_ptr<DBuf<double>>> tmp;
+};
+static std::map<const ts_op*, OpScratch> g_scratch;
+
+static double* iface_tmp(const ts_op* op, int lam) {
+    auto& sc = g_scratch[op];
+    auto& b = sc.tmp[lam];
+    if (!b) {
+        b = std::make_unique<DBuf<double>>();
+        const Level& L = op->mesh->m.level(lam);
+        int mx = 1;
+        for (int p = 0; p < N_IF_PHASES; p++) mx = std::max(mx, L.n_phase[p]);
+        b->alloc(mx);
+    }
+    return b->p;
+}
+
+// y = L x (mode 0) or y = f - L x (mode 1)
+static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
+                    const void* f, hipStream_t s) {
+    launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s);
+    if (uses_surrogate(op, lam))
+        launch_volume(op, lam, dtype, mode, x, y, f, 0, s);
+    else
+        launch_ifem_volume(op, lam, dtype == TS_F16W ? TS_F32 : dtype, mode, x, y, f, 0, s);
+}
+
+static void gs_sweep(const ts_op* op, int lam, int dtype, const void* f, void* u, hipStream_t s) {
+    double* tmp = iface_tmp(op, lam);
+    const int vd = dtype == TS_F16W ? TS_F32 : dtype;
+    for (int p = 0; p < N_IF_PHASES; p++) {
+        launch_iface(op, lam, vd, 2, u, u, f, p, tmp, s);
+        launch_iface_scatter(op, lam, vd, p, tmp, u, s);
+    }
+    const bool sur = uses_surrogate(op, lam);
+    for (int c = 0; c < 4; c++) {
+        if (sur)
+            launch_volume(op, lam, dtype, 2, u, u, f, c, s);
+        else
+            launch_ifem_volume(op, lam, vd, 2, u, u, f, c, s);
+    }
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+// ------------------------------------------------------------------ solver
+
+struct ts_solver {
+    ts_op* op = nullptr;
+    int L = 0;
+    ts_solve_params p{};
+    // per level vectors for the V-cycle, by dtype: 0 FP64, 1 FP32
+    std::map<int, std::unique_ptr<DBuf<double>>> f64, u64, r64;
+    std::map<int, std::unique_ptr<DBuf<float>>> f32, u32, r32;
+    // coarsest level
+    int n0 = 0;
+    DBuf<double> AinvT, cwork;
+    DBuf<int> c_off;
+    DBuf<int64_t> c_slot;
+    // outer iteration
+    DBuf<double> r_outer;
+    DBuf<float> r_in, e_in;
+    DBuf<double> partial, nrm;
+};
+
+namespace ts {
+
+template <class X>
+static X* vec(std::map<int, std::unique_ptr<DBuf<X>>>& m, int lam, int64_t n) {
+    auto& b = m[lam];
+    if (!b) {
+        b = std::make_unique<DBuf<X>>();
+        b->alloc(n);
+    }
+    return b->p;
+}
+
+static void coarse_setup(ts_solver* sv, hipStream_t s) {
+    Mesh& M = sv->op->mesh->m;
+    const int lam = 2;
+    Level& L = M.level(lam);
+    const int N = L.N;
+    // free nodes: free lower-primitive nodes (canonical order), then the one
+    // interior node of every macro
+    std::vector<int> off_if;
+    std::vector<int4> cp_if;
+    std::vector<unsigned char> flag;
+    {
+        std::vector<int> o(L.n_if + 1);
+        std::vector<int4> c(L.if_copy.n);
+        flag.resize(L.n_if);
+        TS_HIP(hipMemcpy(o.data(), L.if_off.p, o.size() * sizeof(int), hipMemcpyDeviceToHost));
+        TS_HIP(hipMemcpy(c.data(), L.if_copy.p, c.size() * sizeof(int4), hipMemcpyDeviceToHost));
+        TS_HIP(hipMemcpy(flag.data(), L.if_flag.p, flag.size(), hipMemcpyDeviceToHost));
+        off_if = o;
+        cp_if = c;
+    }
+    std::vector<int> off{0};
+    std::vector<int4> cp;
+    std::vector<int64_t> slot;
+    std::vector<int> slot_free(L.len, -1);
+    int n = 0;
+    auto add_copy = [&](int4 q) {
+        cp.push_back(q);
+        const int64_t sl = (int64_t)q.x * L.B + bidx(N, q.y, q.z, q.w);
+        slot.push_back(sl);
+        slot_free[sl] = n;
+    };
+    for (int64_t t = 0; t < L.n_if; t++) {
+        if (flag[t] & 1) continue;
+        for (int c = off_if[t]; c < off_if[t + 1]; c++) add_copy(cp_if[c]);
+        n++;
+        off.push_back((int)cp.size());
+    }
+    for (int64_t m = 0; m < M.nt; m++) {
+        add_copy(make_int4((int)m, 1, 1, 1));
+        n++;
+        off.push_back((int)cp.size());
+    }
+    sv->n0 = n;
+    DBuf<int> d_off, d_sf;
+    DBuf<int4> d_cp;
+    d_off.upload(off);
+    d_cp.upload(cp);
+    d_sf.upload(slot_free);
+    sv->c_off.upload(off);
+    sv->c_slot.upload(slot);
+    DBuf<double> A, col;
+    A.alloc((size_t)n * n);
+    col.alloc(n);
+    TS_HIP(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), s));
+    launch_dense_assemble_cp(M, lam, d_off.p, d_cp.p, n, d_sf.p, A.p, s);
+    for (int k = 0; k < n; k++) launch_gj_step(A.p, col.p, n, k, s);
+    TS_HIP(hipGetLastError());
+    sv->AinvT.alloc((size_t)n * n);
+    launch_transpose(A.p, sv->AinvT.p, n, s);
+    sv->cwork.alloc(2 * (size_t)n);
+    TS_HIP(hipStreamSynchronize(s));
+}
+
+template <class X>
+static void vcycle_t(ts_solver* sv, int lam, int dtype, const X* f, X* u, hipStream_t s,
+                     std::map<int, std::unique_ptr<DBuf<X>>>& F,
+                     std::map<int, std::unique_ptr<DBuf<X>>>& U,
+                     std::map<int, std::unique_ptr<DBuf<X>>>& R) {
+    Mesh& M = sv->op->mesh->m;
+    const int vd = dtype == TS_F64 ? TS_F64 : TS_F32;
+    if (lam == 2) {
+        launch_fill(u, vd, M.level(2).len, 0.0, s);
+        launch_coarse_solve(sv->AinvT.p, sv->n0, nullptr, sv->c_off.p, sv->c_slot.p, vd, f, u,
+                            sv->cwork.p, s);
+        return;
+    }
+    const Level& Lf = M.level(lam);
+    const Level& Lc = M.level(lam - 1);
+    for (int k = 0; k < sv->p.nu1; k++) gs_sweep(sv->op, lam, dtype, f, u, s);
+    X* r = vec(R, lam, Lf.len);
+    op_rows(sv->op, lam, dtype, 1, u, r, f, s);
+    X* fc = vec(F, lam - 1, Lc.len);
+    X* uc = vec(U, lam - 1, Lc.len);
+    launch_restrict(M, lam, vd, r, fc, s);
+    vcycle_t<X>(sv, lam - 1, dtype, fc, uc, s, F, U, R);
+    launch_prolongate_add(M, lam, vd, uc, u, s);
+    for (int k = 0; k < sv->p.nu2; k++) gs_sweep(sv->op, lam, dtype, f, u, s);
+}
+
+static void vcycle(ts_solver* sv, int dtype, const void* f, void* u, hipStream_t s) {
+    if (dtype == TS_F64)
+        vcycle_t<double>(sv, sv->L, dtype, (const double*)f, (double*)u, s, sv->f64, sv->u64, sv->r64);
+    else
+        vcycle_t<float>(sv, sv->L, dtype, (const float*)f, (float*)u, s, sv->f32, sv->u32, sv->r32);
+}
+
+static double norm2(ts_solver* sv, int dtype, const void* x, hipStream_t s) {
+    Mesh& M = sv->op->mesh->m;
+    launch_norm2_free(M, sv->L, dtype, x, sv->partial.p, sv->nrm.p, s);
+    double h = 0;
+    TS_HIP(hipMemcpyAsync(&h, sv->nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    TS_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+}  // namespace ts
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* ts_last_error(void) { return g_last_error.c_str(); }
+
+int ts_mesh_create(const double* vtx, int64_t nv, const int64_t* tet, int64_t nt, int geom,
+                   ts_mesh** out) {
+    return guarded([&] {
+        TS_REQUIRE(vtx && tet && out && nv >= 4 && nt >= 1, TS_EINVAL, "bad mesh arguments");
+        TS_REQUIRE(geom == TS_GEOM_SHELL || geom == TS_GEOM_AFFINE, TS_EINVAL, "bad geometry kind");
+        auto* m = new ts_mesh();
+        try {
+            m->m.nv = nv;
+            m->m.nt = nt;
+            m->m.geom = geom;
+            m->m.vtx.assign(vtx, vtx + 3 * nv);
+            m->m.tet.assign(tet, tet + 4 * nt);
+            TS_HIP(hipGetDevice(&m->m.device));
+            build_topology(m->m);
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+int ts_mesh_destroy(ts_mesh* mesh) {
+    return guarded([&] { delete mesh; });
+}
+
+int ts_layout(ts_mesh* mesh, int level, ts_layout_info* out) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && out, TS_EINVAL, "null argument");
+        Level& L = mesh->m.level(level);
+        out->level = level;
+        out->N = L.N;
+        out->n_macros = mesh->m.nt;
+        out->block_size = L.B;
+        out->vec_len = L.len;
+        out->n_unique = L.n_unique;
+        out->n_free = L.n_free;
+        out->n_volume = mesh->m.nt * (int64_t)(L.N - 1) * (L.N - 2) * (L.N - 3) / 6;
+    });
+}
+
+int ts_canon_to_block(ts_mesh* mesh, int level, const double* canon, double* block, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && canon && block, TS_EINVAL, "null argument");
+        launch_canon_to_block(mesh->m, level, canon, block, S(s));
+    });
+}
+
+int ts_block_to_canon(ts_mesh* mesh, int level, const double* block, double* canon, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && canon && block, TS_EINVAL, "null argument");
+        launch_block_to_canon(mesh->m, level, block, canon, S(s));
+    });
+}
+
+int ts_node_coords(ts_mesh* mesh, int level, double* xyz, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && xyz, TS_EINVAL, "null argument");
+        launch_coords(mesh->m, level, xyz, S(s));
+    });
+}
+
+int ts_rhs(ts_mesh* mesh, int level, int kind, const double* params, int nparams, double* f,
+           ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && f, TS_EINVAL, "null argument");
+        TS_REQUIRE(kind >= 0 && kind <= 2, TS_EINVAL, "bad rhs kind");
+        TS_REQUIRE(kind != TS_RHS_MANUFACTURED || (params && nparams >= 2), TS_EINVAL,
+                   "manufactured rhs needs {r1, r2}");
+        TS_REQUIRE(nparams >= 0 && nparams <= 4096, TS_EINVAL, "bad parameter count");
+        for (int i = 0; i < nparams; i++)
+            TS_REQUIRE(std::isfinite(params[i]), TS_ENONFINITE, "non-finite rhs parameter");
+        std::vector<double> h(params ? params : nullptr, params ? params + nparams : nullptr);
+        if (h.empty()) h.push_back(0.0);
+        DBuf<double> d;
+        d.upload(h);
+        launch_rhs(mesh->m, level, kind, d.p, nparams, f, S(s));
+        TS_HIP(hipStreamSynchronize(S(s)));
+    });
+}
+
+int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream s, ts_op** out) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && p && out, TS_EINVAL, "null argument");
+        TS_REQUIRE(max_level >= 2 && max_level <= 9, TS_EINVAL, "max_level must be in 2..9");
+        TS_REQUIRE(p->method == TS_IFEM || p->method == TS_LSQP || p->method == TS_IPOLY, TS_EINVAL,
+                   "bad method");
+        if (p->method != TS_IFEM) {
+            TS_REQUIRE(p->q >= 1 && p->q <= 4, TS_EINVAL, "degree q must be in 1..4");
+            TS_REQUIRE(p->method != TS_IPOLY || p->q == 2, TS_EINVAL, "IPOLY is defined for q = 2");
+            TS_REQUIRE(p->center == TS_CENTER_POLY || p->center == TS_CENTER_ROWSUM, TS_EINVAL,
+                       "bad centre mode");
+        }
+        auto* op = new ts_op();
+        try {
+            op->mesh = mesh;
+            op->p = *p;
+            op->max_level = max_level;
+            op->mq = p->method == TS_IFEM ? 0 : mq_of(p->q);
+            for (int lam = 2; lam <= max_level; lam++) setup_level(op, lam, S(s));
+        } catch (...) {
+            delete op;
+            throw;
+        }
+        *out = op;
+    });
+}
+
+int ts_op_destroy(ts_op* op) {
+    return guarded([&] {
+        g_scratch.erase(op);
+        delete op;
+    });
+}
+
+int ts_op_coeffs_export(ts_op* op, int level, double* host, size_t n) {
+    return guarded([&] {
+        TS_REQUIRE(op && host, TS_EINVAL, "null argument");
+        TS_REQUIRE(uses_surrogate(op, level), TS_EINVAL, "no surrogate coefficients on this level");
+        const size_t need = (size_t)op->mesh->m.nt * NW * op->mq;
+        TS_REQUIRE(n >= need, TS_EINVAL, "buffer too small");
+        TS_HIP(hipMemcpy(host, op->lv[level]->coef64.p, need * sizeof(double), hipMemcpyDeviceToHost));
+    });
+}
+
+int ts_op_coeffs_import(ts_op* op, int level, const double* host, size_t n) {
+    return guarded([&] {
+        TS_REQUIRE(op && host, TS_EINVAL, "null argument");
+        TS_REQUIRE(uses_surrogate(op, level), TS_EINVAL, "no surrogate coefficients on this level");
+        const size_t need = (size_t)op->mesh->m.nt * NW * op->mq;
+        TS_REQUIRE(n == need, TS_EINVAL, "coefficient count mismatch");
+        std::vector<double> h(host, host + need);
+        for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite coefficient");
+        LevelOp& lo = *op->lv[level];
+        TS_HIP(hipMemcpy(lo.coef64.p, h.data(), need * sizeof(double), hipMemcpyHostToDevice));
+        upload_coef_variants(op, lo, level, h);
+    });
+}
+
+static void check_level(ts_op* op, int level) {
+    TS_REQUIRE(op, TS_EINVAL, "null operator");
+    TS_REQUIRE(level >= 2 && level <= op->max_level, TS_EINVAL, "level outside the operator's range");
+}
+static void check_dtype(int dt) {
+    TS_REQUIRE(dt == TS_F64 || dt == TS_F32 || dt == TS_F16W, TS_EINVAL, "bad dtype");
+}
+
+int ts_apply(ts_op* op, int level, int dtype, const void* x, void* y, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        check_dtype(dtype);
+        TS_REQUIRE(x && y && x != y, TS_EINVAL, "x and y must be distinct device vectors");
+        op_rows(op, level, dtype, 0, x, y, nullptr, S(s));
+    });
+}
+
+int ts_apply_volume(ts_op* op, int level, int dtype, const void* x, void* y, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        check_dtype(dtype);
+        TS_REQUIRE(x && y && x != y, TS_EINVAL, "x and y must be distinct device vectors");
+        if (uses_surrogate(op, level))
+            launch_volume(op, level, dtype, 0, x, y, nullptr, 0, S(s));
+        else
+            launch_ifem_volume(op, level, dtype == TS_F16W ? TS_F32 : dtype, 0, x, y, nullptr, 0, S(s));
+    });
+}
+
+int ts_residual(ts_op* op, int level, int dtype, const void* f, const void* u, void* r, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        check_dtype(dtype);
+        TS_REQUIRE(f && u && r && r != u && r != f, TS_EINVAL, "bad vectors");
+        op_rows(op, level, dtype, 1, u, r, f, S(s));
+    });
+}
+
+int ts_smooth(ts_op* op, int level, int dtype, const void* f, void* u, int sweeps, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        check_dtype(dtype);
+        TS_REQUIRE(f && u && f != u && sweeps >= 0, TS_EINVAL, "bad arguments");
+        for (int k = 0; k < sweeps; k++) gs_sweep(op, level, dtype, f, u, S(s));
+    });
+}
+
+int ts_restrict(ts_op* op, int level, int dtype, const void* rf, void* rc, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        TS_REQUIRE(level >= 3, TS_EINVAL, "no coarser level");
+        check_dtype(dtype);
+        launch_restrict(op->mesh->m, level, dtype == TS_F64 ? TS_F64 : TS_F32, rf, rc, S(s));
+    });
+}
+
+int ts_prolongate_add(ts_op* op, int level, int dtype, const void* uc, void* uf, ts_stream s) {
+    return guarded([&] {
+        check_level(op, level);
+        TS_REQUIRE(level >= 3, TS_EINVAL, "no coarser level");
+        check_dtype(dtype);
+        launch_prolongate_add(op->mesh->m, level, dtype == TS_F64 ? TS_F64 : TS_F32, uc, uf, S(s));
+    });
+}
+
+int ts_norm2(ts_mesh* mesh, int level, int dtype, const void* x, double* out, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && x && out, TS_EINVAL, "null argument");
+        check_dtype(dtype);
+        DBuf<double> part, r;
+        part.alloc(norm_partial_count(mesh->m, level));
+        r.alloc(1);
+        launch_norm2_free(mesh->m, level, dtype == TS_F64 ? TS_F64 : TS_F32, x, part.p, r.p, S(s));
+        TS_HIP(hipMemcpyAsync(out, r.p, sizeof(double), hipMemcpyDeviceToHost, S(s)));
+        TS_HIP(hipStreamSynchronize(S(s)));
+    });
+}
+
+int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver** out) {
+    return guarded([&] {
+        check_level(op, level);
+        TS_REQUIRE(p && out, TS_EINVAL, "null argument");
+        TS_REQUIRE(level >= 3, TS_EINVAL, "the solver needs at least one level above level 2");
+        TS_REQUIRE(p->nu1 >= 0 && p->nu2 >= 0 && p->nu1 + p->nu2 > 0, TS_EINVAL, "bad smoothing counts");
+        TS_REQUIRE(p->max_cycles > 0 && p->max_cycles < TS_MAX_HIST - 1, TS_EINVAL, "bad max_cycles");
+        TS_REQUIRE(p->rtol > 0, TS_EINVAL, "rtol must be positive");
+        check_dtype(p->precision);
+        auto* sv = new ts_solver();
+        try {
+            sv->op = op;
+            sv->L = level;
+            sv->p = *p;
+            if (sv->p.diverge_window <= 0) sv->p.diverge_window = 3;
+            hipStream_t s = nullptr;
+            coarse_setup(sv, s);
+            Mesh& M = op->mesh->m;
+            sv->partial.alloc(norm_partial_count(M, level));
+            sv->nrm.alloc(1);
+        } catch (...) {
+            delete sv;
+            throw;
+        }
+        *out = sv;
+    });
+}
+
+int ts_solver_destroy(ts_solver* sv) {
+    return guarded([&] { delete sv; });
+}
+
+int ts_vcycle(ts_solver* sv, int dtype, const void* f, void* u, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(sv && f && u && f != u, TS_EINVAL, "bad arguments");
+        check_dtype(dtype);
+        vcycle(sv, dtype, f, u, S(s));
+    });
+}
+
+int ts_solve(ts_solver* sv, const double* f, double* u, ts_solve_info* info, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(sv && f && u && info, TS_EINVAL, "null argument");
+        hipStream_t st = S(s);
+        Mesh& M = sv->op->mesh->m;
+        const Level& L = M.level(sv->L);
+        memset(info, 0, sizeof(*info));
+        const double nf = norm2(sv, TS_F64, f, st);
+        TS_REQUIRE(std::isfinite(nf), TS_ENONFINITE, "right-hand side is not finite");
+        if (nf == 0.0) {
+            launch_fill(u, TS_F64, L.len, 0.0, st);
+            TS_HIP(hipStreamSynchronize(st));
+            info->status = TS_OK;
+            return;
+        }
+        const int prec = sv->p.precision;
+        if (prec != TS_F64 && !sv->r_outer.p) {
+            sv->r_outer.alloc(L.len);
+            sv->r_in.alloc(L.len);
+            sv->e_in.alloc(L.len);
+        }
+        double* r = sv->r_outer.p;
+        if (prec == TS_F64 && !r) {
+            sv->r_outer.alloc(L.len);
+            r = sv->r_outer.p;
+        }
+        op_rows(sv->op, sv->L, TS_F64, 1, u, r, f, st);
+        double rel = norm2(sv, TS_F64, r, st) / nf;
+        info->hist[info->n_hist++] = rel;
+        int ups = 0;
+        double prev = rel;
+        int status = TS_OK;
+        int c = 0;
+        while (rel > sv->p.rtol) {
+            if (c >= sv->p.max_cycles) {
+                status = TS_ENOCONV;
+                break;
+            }
+            if (prec == TS_F64) {
+                vcycle(sv, TS_F64, f, u, st);
+            } else {
+                launch_cast(r, TS_F64, sv->r_in.p, TS_F32, L.len, st);
+                launch_fill(sv->e_in.p, TS_F32, L.len, 0.0, st);
+                vcycle(sv, prec, sv->r_in.p, sv->e_in.p, st);
+                launch_axpy(1.0, sv->e_in.p, TS_F32, u, L.len, st);
+            }
+            c++;
+            op_rows(sv->op, sv->L, TS_F64, 1, u, r, f, st);
+            rel = norm2(sv, TS_F64, r, st) / nf;
+            if (info->n_hist < TS_MAX_HIST) info->hist[info->n_hist++] = rel;
+            if (!std::isfinite(rel)) {
+                status = TS_ENONFINITE;
+                break;
+            }
+            ups = rel > prev ? ups + 1 : 0;
+            prev = rel;
+            if (ups >= sv->p.diverge_window) {
+                status = TS_ENOCONV;
+                break;
+            }
+        }
+        info->cycles = c;
+        info->rel_residual = rel;
+        info->status = status;
+        if (status != TS_OK)
+            throw Error{status, status == TS_ENONFINITE ? "iterate became non-finite"
+                                                        : "no convergence to the tolerance"};
+    });
+}
+
+}  // extern "C"

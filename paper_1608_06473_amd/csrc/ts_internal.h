@@ -1,0 +1,199 @@
+// Internal data structures of the two-scale library (host side) and the
+// kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <array>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ts_geom.h"
+#include "../../include/twoscale.h"
+
+namespace ts {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct Error {
+    int code;
+    std::string msg;
+};
+#define TS_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            throw ::ts::Error{TS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define TS_REQUIRE(cond, code, msg)                        \
+    do {                                                   \
+        if (!(cond)) throw ::ts::Error{(code), (msg)};     \
+    } while (0)
+
+// ------------------------------------------------------------ device buffer
+template <typename X>
+struct DBuf {
+    X* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        reset();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(&p, count * sizeof(X));
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(X)) + " bytes failed"};
+        }
+        n = count;
+    }
+    void upload(const std::vector<X>& h) {
+        alloc(h.size());
+        if (!h.empty()) TS_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
+    }
+};
+
+// Per-macro topology record on the device: global vertex ids, edge and face
+// ids of the primitives (local edge order (0,1),(0,2),(0,3),(1,2),(1,3),(2,3);
+// face o is opposite local vertex o), which local vertex of each edge has the
+// larger global id, the local vertices of each face sorted by global id,
+// Dirichlet flags and macro multiplicities of each primitive.
+struct MacroTopo {
+    int64_t vg[4];
+    int64_t e[6];
+    int64_t f[4];
+    signed char ehi[6];      // local vertex (0..3) with the larger global id
+    signed char elo[6];
+    signed char fs[4][3];    // face o: local vertices sorted by global id
+    unsigned char vdir[4], edir[6], fdir[4];
+    unsigned char emult[6], fmult[4];
+    unsigned char pad[2];
+};
+
+// GS phases of the lower primitives: 0 vertices, 1-2 edges (a mod 2), 3-5
+// faces ((a + 2b) mod 3 in the face frame).
+constexpr int N_IF_PHASES = 6;
+
+// Per-level layout and interface maps.
+struct Level {
+    int lam = 0, N = 0;
+    int64_t B = 0, len = 0;       // block size, vector length (n_macros * B)
+    int64_t n_unique = 0, n_free = 0;
+    int64_t n_if = 0;             // unique lower-primitive nodes (incl. Dirichlet)
+    DBuf<int> if_off;             // n_if + 1
+    DBuf<int4> if_copy;           // (macro, i, j, k)
+    DBuf<unsigned char> if_flag;  // bit 0: Dirichlet; bits 1-3: GS phase
+    DBuf<int> phase_list[N_IF_PHASES];
+    int n_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
+    DBuf<int> if_free;            // free interface nodes (for norms)
+    int n_if_free = 0;
+    // volume tiles: (k0, first position in plane k0's interior triangle)
+    DBuf<int2> tiles;
+    int n_tiles = 0;
+    // all-slot tiles: (plane k, first slot of a chunk of plane k)
+    DBuf<int2> slot_tiles;
+    int n_slot_tiles = 0;
+};
+
+constexpr int VOL_R = 8;       // planes per volume tile
+constexpr int VOL_THREADS = 256;
+
+struct Mesh {
+    int64_t nv = 0, nt = 0, ne = 0, nf = 0;
+    int geom = TS_GEOM_SHELL;
+    std::vector<double> vtx;
+    std::vector<int64_t> tet;
+    std::vector<std::array<int64_t, 2>> edges;
+    std::vector<std::array<int64_t, 3>> faces;
+    std::vector<unsigned char> vdir, edir, fdir;
+    std::vector<std::vector<int64_t>> v_tets, e_tets, f_tets;
+    std::vector<MacroTopo> topo;
+    std::vector<MacroGeom> geomh;
+    DBuf<MacroGeom> d_geom;
+    DBuf<MacroTopo> d_topo;
+    std::map<int, std::unique_ptr<Level>> levels;
+    int device = 0;
+
+    Level& level(int lam);
+    int64_t num_unique(int N) const {
+        return nv + ne * (N - 1) + nf * (int64_t)(N - 1) * (N - 2) / 2 +
+               nt * (int64_t)(N - 1) * (N - 2) * (N - 3) / 6;
+    }
+};
+
+void build_topology(Mesh& M);
+
+// ------------------------------------------------------------ operators
+struct LevelOp {
+    int lam = 0;
+    DBuf<double> coef64;   // [nt][15][mq]
+    DBuf<float> coef32;
+    DBuf<float> coef16s;   // FP16-weight variant: coefficients pre-scaled by N
+    bool has_coef = false;
+};
+
+}  // namespace ts
+
+struct ts_mesh {
+    ts::Mesh m;
+};
+
+struct ts_op {
+    ts_mesh* mesh = nullptr;
+    ts_op_params p{};
+    int max_level = 0;
+    int mq = 0;
+    std::map<int, std::unique_ptr<ts::LevelOp>> lv;
+};
+
+namespace ts {
+
+// ------------------------------------------------------------ kernel launchers
+// vector dtype codes follow TS_F64 / TS_F32 / TS_F16W (the last two use
+// float vectors).
+void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
+                   const void* f, int colour, hipStream_t s);
+void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
+                  const void* f, int phase, double* tmp, hipStream_t s);
+void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
+                          void* u, hipStream_t s);
+void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
+                        const void* f, int colour, hipStream_t s);
+void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* rc, hipStream_t s);
+void launch_prolongate_add(const Mesh& M, int lam_f, int dtype, const void* uc, void* uf,
+                           hipStream_t s);
+void launch_fill(void* x, int dtype, int64_t n, double v, hipStream_t s);
+void launch_cast(const void* src, int dsrc, void* dst, int ddst, int64_t n, hipStream_t s);
+void launch_axpy(double a, const void* x, int dx, double* y, int64_t n, hipStream_t s);
+double norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
+                  hipStream_t s);  // synchronising
+int64_t norm_partial_count(const Mesh& M, int lam);
+void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
+                       double* out, hipStream_t s);
+void launch_canon_to_block(const Mesh& M, int lam, const double* c, double* b, hipStream_t s);
+void launch_block_to_canon(const Mesh& M, int lam, const double* b, double* c, hipStream_t s);
+void launch_coords(const Mesh& M, int lam, double* xyz, hipStream_t s);
+void launch_rhs(const Mesh& M, int lam, int kind, const double* dpar, int npar, double* f,
+                hipStream_t s);
+void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s);
+void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt, double* coef,
+                double* work, hipStream_t s);
+void launch_dense_assemble_cp(const Mesh& M, int lam, const int* off, const int4* cp, int nfree,
+                              const int* slot_free, double* A, hipStream_t s);
+void launch_transpose(const double* a, double* b, int n, hipStream_t s);
+void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s);
+void launch_coarse_solve(const double* Ainv, int n, const int* free_first, const int* cp_off,
+                         const int64_t* cp_slot, int dtype, const void* f, void* u,
+                         double* work, hipStream_t s);
+
+}  // namespace ts

@@ -1,0 +1,255 @@
+// Host side: macro-mesh topology (edges, faces, incidence, Dirichlet flags)
+// and the per-level layout (lower-primitive copy maps, GS phase lists and
+// volume tiles).  Sec. 2.3: nodes are grouped into vertex, edge, face and
+// volume primitives; lower primitives keep element-wise assembly.
+#include <math.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "ts_internal.h"
+
+namespace ts {
+
+namespace {
+
+const int EDGE_LOC[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+template <size_t K>
+int64_t find_sorted(const std::vector<std::array<int64_t, K>>& v, std::array<int64_t, K> key) {
+    auto it = std::lower_bound(v.begin(), v.end(), key);
+    if (it == v.end() || *it != key) return -1;
+    return it - v.begin();
+}
+
+}  // namespace
+
+void build_topology(Mesh& M) {
+    const int64_t nt = M.nt, nv = M.nv;
+    for (int64_t i = 0; i < 4 * nt; i++)
+        TS_REQUIRE(M.tet[i] >= 0 && M.tet[i] < nv, TS_EINVAL, "tetrahedron vertex id out of range");
+    // edges and faces as sorted id tuples
+    std::vector<std::array<int64_t, 2>> E;
+    std::vector<std::array<int64_t, 3>> F;
+    E.reserve(6 * nt);
+    F.reserve(4 * nt);
+    for (int64_t t = 0; t < nt; t++) {
+        const int64_t* g = &M.tet[4 * t];
+        for (int a = 0; a < 4; a++)
+            for (int b = a + 1; b < 4; b++) {
+                TS_REQUIRE(g[a] != g[b], TS_EINVAL, "repeated vertex in a tetrahedron");
+                E.push_back({std::min(g[a], g[b]), std::max(g[a], g[b])});
+            }
+        for (int o = 0; o < 4; o++) {
+            std::array<int64_t, 3> f;
+            int c = 0;
+            for (int a = 0; a < 4; a++)
+                if (a != o) f[c++] = g[a];
+            std::sort(f.begin(), f.end());
+            F.push_back(f);
+        }
+    }
+    std::sort(E.begin(), E.end());
+    E.erase(std::unique(E.begin(), E.end()), E.end());
+    std::sort(F.begin(), F.end());
+    F.erase(std::unique(F.begin(), F.end()), F.end());
+    M.edges = E;
+    M.faces = F;
+    M.ne = E.size();
+    M.nf = F.size();
+    M.v_tets.assign(nv, {});
+    M.e_tets.assign(M.ne, {});
+    M.f_tets.assign(M.nf, {});
+    M.topo.assign(nt, MacroTopo{});
+    for (int64_t t = 0; t < nt; t++) {
+        const int64_t* g = &M.tet[4 * t];
+        MacroTopo& T = M.topo[t];
+        for (int a = 0; a < 4; a++) {
+            T.vg[a] = g[a];
+            M.v_tets[g[a]].push_back(t);
+        }
+        for (int e = 0; e < 6; e++) {
+            int a = EDGE_LOC[e][0], b = EDGE_LOC[e][1];
+            T.e[e] = find_sorted(E, {std::min(g[a], g[b]), std::max(g[a], g[b])});
+            T.ehi[e] = (signed char)(g[a] > g[b] ? a : b);
+            T.elo[e] = (signed char)(g[a] > g[b] ? b : a);
+            M.e_tets[T.e[e]].push_back(t);
+        }
+        for (int o = 0; o < 4; o++) {
+            int loc[3], c = 0;
+            for (int a = 0; a < 4; a++)
+                if (a != o) loc[c++] = a;
+            std::sort(loc, loc + 3, [&](int x, int y) { return g[x] < g[y]; });
+            std::array<int64_t, 3> key = {g[loc[0]], g[loc[1]], g[loc[2]]};
+            T.f[o] = find_sorted(F, key);
+            for (int q = 0; q < 3; q++) T.fs[o][q] = (signed char)loc[q];
+            M.f_tets[T.f[o]].push_back(t);
+        }
+    }
+    for (int64_t f = 0; f < M.nf; f++)
+        TS_REQUIRE(M.f_tets[f].size() <= 2, TS_EINVAL, "a face is shared by more than two macros");
+    // Dirichlet: all primitives of boundary faces (faces of one macro)
+    M.vdir.assign(nv, 0);
+    M.edir.assign(M.ne, 0);
+    M.fdir.assign(M.nf, 0);
+    for (int64_t f = 0; f < M.nf; f++) {
+        if (M.f_tets[f].size() != 1) continue;
+        const auto& k = F[f];
+        M.fdir[f] = 1;
+        for (int a = 0; a < 3; a++) M.vdir[k[a]] = 1;
+        M.edir[find_sorted(E, {k[0], k[1]})] = 1;
+        M.edir[find_sorted(E, {k[0], k[2]})] = 1;
+        M.edir[find_sorted(E, {k[1], k[2]})] = 1;
+    }
+    // per-macro flags, multiplicities and geometry
+    M.geomh.assign(nt, MacroGeom{});
+    for (int64_t t = 0; t < nt; t++) {
+        MacroTopo& T = M.topo[t];
+        for (int a = 0; a < 4; a++) T.vdir[a] = M.vdir[T.vg[a]];
+        for (int e = 0; e < 6; e++) {
+            T.edir[e] = M.edir[T.e[e]];
+            T.emult[e] = (unsigned char)std::min<size_t>(255, M.e_tets[T.e[e]].size());
+        }
+        for (int o = 0; o < 4; o++) {
+            T.fdir[o] = M.fdir[T.f[o]];
+            T.fmult[o] = (unsigned char)M.f_tets[T.f[o]].size();
+        }
+        MacroGeom& G = M.geomh[t];
+        const int64_t* g = &M.tet[4 * t];
+        for (int a = 0; a < 4; a++) {
+            double r2 = 0;
+            for (int d = 0; d < 3; d++) {
+                G.v[a][d] = M.vtx[3 * g[a] + d];
+                r2 += G.v[a][d] * G.v[a][d];
+            }
+            G.r[a] = sqrt(r2);
+            G.ord[a] = a;
+        }
+        std::sort(G.ord, G.ord + 4, [&](int x, int y) { return g[x] < g[y]; });
+        G.affine = M.geom == TS_GEOM_AFFINE ? 1 : 0;
+        // degenerate macro check
+        double e1[3], e2[3], e3[3];
+        for (int d = 0; d < 3; d++) {
+            e1[d] = G.v[1][d] - G.v[0][d];
+            e2[d] = G.v[2][d] - G.v[0][d];
+            e3[d] = G.v[3][d] - G.v[0][d];
+        }
+        double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                     e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+        TS_REQUIRE(fabs(det) > 1e-300, TS_EINVAL, "degenerate macro tetrahedron");
+    }
+    M.d_geom.upload(M.geomh);
+    M.d_topo.upload(M.topo);
+}
+
+Level& Mesh::level(int lam) {
+    auto it = levels.find(lam);
+    if (it != levels.end()) return *it->second;
+    TS_REQUIRE(lam >= 2 && lam <= 9, TS_EINVAL, "level must be in 2..9");
+    auto L = std::make_unique<Level>();
+    const int N = 1 << lam;
+    L->lam = lam;
+    L->N = N;
+    L->B = block_size(N);
+    L->len = nt * L->B;
+    L->n_unique = num_unique(N);
+
+    // lower-primitive nodes in canonical order with their copies
+    const int64_t nF = (int64_t)(N - 1) * (N - 2) / 2;
+    const int64_t n_if = nv + ne * (N - 1) + nf * nF;
+    TS_REQUIRE(n_if < (int64_t)1 << 31, TS_EINVAL, "too many interface nodes for this level");
+    std::vector<int> off;
+    std::vector<int4> cp;
+    std::vector<unsigned char> flag;
+    off.reserve(n_if + 1);
+    flag.reserve(n_if);
+    off.push_back(0);
+    auto push = [&](int64_t t, const int mu[4]) {
+        cp.push_back(make_int4((int)t, mu[1], mu[2], mu[3]));
+    };
+    auto pos_in = [&](int64_t t, int64_t gid) {
+        for (int a = 0; a < 4; a++)
+            if (tet[4 * t + a] == gid) return a;
+        return -1;
+    };
+    int64_t n_free_if = 0;
+    for (int64_t g = 0; g < nv; g++) {
+        for (int64_t t : v_tets[g]) {
+            int mu[4] = {0, 0, 0, 0};
+            mu[pos_in(t, g)] = N;
+            push(t, mu);
+        }
+        off.push_back((int)cp.size());
+        flag.push_back((unsigned char)(vdir[g] | (0 << 1)));
+        n_free_if += !vdir[g];
+    }
+    for (int64_t e = 0; e < ne; e++)
+        for (int a = 1; a <= N - 1; a++) {
+            for (int64_t t : e_tets[e]) {
+                int mu[4] = {0, 0, 0, 0};
+                mu[pos_in(t, edges[e][0])] = N - a;
+                mu[pos_in(t, edges[e][1])] = a;
+                push(t, mu);
+            }
+            off.push_back((int)cp.size());
+            flag.push_back((unsigned char)(edir[e] | ((1 + a % 2) << 1)));
+            n_free_if += !edir[e];
+        }
+    for (int64_t f = 0; f < nf; f++)
+        for (int b = 1; b <= N - 2; b++)
+            for (int a = 1; a <= N - 1 - b; a++) {
+                for (int64_t t : f_tets[f]) {
+                    int mu[4] = {0, 0, 0, 0};
+                    mu[pos_in(t, faces[f][0])] = N - a - b;
+                    mu[pos_in(t, faces[f][1])] = a;
+                    mu[pos_in(t, faces[f][2])] = b;
+                    push(t, mu);
+                }
+                off.push_back((int)cp.size());
+                flag.push_back((unsigned char)(fdir[f] | ((3 + (a + 2 * b) % 3) << 1)));
+                n_free_if += !fdir[f];
+            }
+    L->n_if = n_if;
+    L->n_free = n_free_if + nt * (int64_t)(N - 1) * (N - 2) * (N - 3) / 6;
+    L->if_off.upload(off);
+    L->if_copy.upload(cp);
+    L->if_flag.upload(flag);
+    std::vector<int> lists[N_IF_PHASES];
+    std::vector<int> freel;
+    for (int64_t n = 0; n < n_if; n++) {
+        if (flag[n] & 1) continue;
+        lists[flag[n] >> 1].push_back((int)n);
+        freel.push_back((int)n);
+    }
+    for (int p = 0; p < N_IF_PHASES; p++) {
+        L->phase_list[p].upload(lists[p]);
+        L->n_phase[p] = (int)lists[p].size();
+    }
+    L->if_free.upload(freel);
+    L->n_if_free = (int)freel.size();
+
+    // volume tiles: planes k0 = 1, 1 + R, ... with chunks of positions of the
+    // interior triangle of plane k0 (i, j >= 1, i + j <= N - 1 - k0)
+    std::vector<int2> tiles;
+    for (int k0 = 1; k0 <= N - 3; k0 += VOL_R) {
+        const int Mr = N - 1 - k0;
+        const int npos = (Mr - 1) * Mr / 2;
+        for (int s = 0; s < npos; s += VOL_THREADS) tiles.push_back(make_int2(k0, s));
+    }
+    L->tiles.upload(tiles);
+    L->n_tiles = (int)tiles.size();
+    // all-slot tiles: every plane k = 0..N in chunks of 256 slots
+    std::vector<int2> st;
+    for (int k = 0; k <= N; k++) {
+        const int64_t n = tri_n(N + 1 - k);
+        for (int64_t s = 0; s < n; s += 256) st.push_back(make_int2(k, (int)s));
+    }
+    L->slot_tiles.upload(st);
+    L->n_slot_tiles = (int)st.size();
+
+    Level& ref = *L;
+    levels[lam] = std::move(L);
+    return ref;
+}
+
+}  // namespace ts

@@ -274,6 +274,7 @@ static void vcycle_t(ts_solver* sv, int lam, int dtype, const X* f, X* u, hipStr
     X* fc = vec(F, lam - 1, Lc.len);
     X* uc = vec(U, lam - 1, Lc.len);
     launch_restrict(M, lam, vd, r, fc, s);
+    launch_fill(uc, vd, Lc.len, 0.0, s);  // zero initial coarse correction
     vcycle_t<X>(sv, lam - 1, dtype, fc, uc, s, F, U, R);
     launch_prolongate_add(M, lam, vd, uc, u, s);
     for (int k = 0; k < sv->p.nu2; k++) gs_sweep(sv->op, lam, dtype, f, u, s);

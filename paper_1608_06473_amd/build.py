@@ -8,12 +8,15 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtwoscale.so")
 SOURCES = ["ts_topology.cpp", "ts_api.cpp", "k_stencil.hip", "k_misc.hip"]
+# the surrogate volume kernel, one unit per (degree q, staging width kpt)
+INST = [(q, k) for q in (1, 2, 3, 4) for k in (2, 4, 8)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -25,31 +28,33 @@ FLAGS = [
 ]
 
 
-def _compile(src, obj):
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-    subprocess.check_call(cmd)
+def build(jobs=8, verbose=True, lib_path=LIB, defines=(), build_dir=None):
+    """Compile all sources (always) and link the shared library.
 
-
-def build(jobs=4, verbose=True):
-    """Compile all sources (always) and link the shared library."""
-    bdir = os.path.join(HERE, "_build")
+    defines: extra preprocessor definitions (tuning constants such as
+    TS_VOL_R, TS_VOL_WAVES) for experiments."""
+    bdir = build_dir or os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = [os.path.join(bdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    units = [(s, os.path.join(bdir, os.path.splitext(s)[0] + ".o"), []) for s in SOURCES]
+    units += [("k_surr_inst.hip", os.path.join(bdir, "k_surr_q%d_k%d.o" % (q, k)),
+               ["TS_Q=%d" % q, "TS_KPT=%d" % k]) for q, k in INST]
+    objs = [u[1] for u in units]
     procs = []
-    for src, obj in zip(SOURCES, objs):
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    for src, obj, extra in units:
+        cmd = ([HIPCC] + FLAGS + ["-D" + d for d in list(defines) + extra] +
+               ["-c", os.path.join(CSRC, src), "-o", obj])
         if verbose:
-            print("[build]", src, flush=True)
+            print("[build]", os.path.basename(obj), flush=True)
         procs.append(subprocess.Popen(cmd))
         while len([p for p in procs if p.poll() is None]) >= jobs:
-            procs[0].wait()
+            time.sleep(0.2)
     rc = [p.wait() for p in procs]
     if any(rc):
-        raise RuntimeError("hipcc failed for " + ", ".join(s for s, r in zip(SOURCES, rc) if r))
-    tmp = LIB + ".tmp"
+        raise RuntimeError("hipcc failed for " + ", ".join(u[1] for u, r in zip(units, rc) if r))
+    tmp = lib_path + ".tmp"
     subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -79,7 +79,6 @@ static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vec
     lo.coef32.upload(f32);
     lo.coef16s.upload(f16s);
     lo.has_coef = true;
-    (void)op;
 }
 
 static void setup_level(ts_op* op, int lam, hipStream_t s) {
@@ -122,7 +121,7 @@ static double* iface_tmp(const ts_op* op, int lam) {
         b = std::make_unique<DBuf<double>>();
         const Level& L = op->mesh->m.level(lam);
         int mx = 1;
-        for (int p = 0; p < N_IF_PHASES; p++) mx = std::max(mx, L.n_phase[p]);
+        for (int p = 0; p < N_IF_PHASES; p++) mx = std::max(mx, L.n_f2_phase[p] + L.n_rest_phase[p]);
         b->alloc(mx);
     }
     return b->p;

@@ -103,9 +103,39 @@ struct Level {
     // all-slot tiles: (plane k, first slot of a chunk of plane k)
     DBuf<int2> slot_tiles;
     int n_slot_tiles = 0;
+    // LDS-staged volume tiles: (k0, j0, j1, i0): rows j0..j1-1 of plane k0's
+    // interior (i0 = 0), or one row j0 from i0 on (i0 >= 1, long rows)
+    DBuf<int4> lds_tiles;
+    int n_lds_tiles = 0;
+    int lds_kpt = 0;              // staged values per thread and plane
+    // fast path for nodes of interior faces (exactly two copies): node ids,
+    // both copies, and their partial stencils as struct of arrays
+    // [copy][w][face node] so that lane loads are coalesced; the remaining
+    // lower-primitive nodes (edges, vertices, Dirichlet faces) go through the
+    // general copy lists
+    int n_f2 = 0;
+    DBuf<int> f2_node;
+    DBuf<int4> f2_cp;             // [2][n_f2]
+    DBuf<double> f2_sten;         // [2][15][n_f2]
+    DBuf<int> rest;               // other lower-primitive nodes (node ids)
+    int n_rest = 0;
+    // per GS phase: positions in the face fast path / in the general lists
+    DBuf<int> f2_phase[N_IF_PHASES];
+    int n_f2_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
+    DBuf<int> rest_phase[N_IF_PHASES];  // node ids
+    int n_rest_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
 };
 
-constexpr int VOL_R = 8;       // planes per volume tile
+#ifndef TS_VOL_R
+#define TS_VOL_R 16
+#endif
+#ifndef TS_VOL_WAVES
+#define TS_VOL_WAVES 2
+#endif
+#ifndef TS_VOL_PF
+#define TS_VOL_PF 4
+#endif
+constexpr int VOL_R = TS_VOL_R;  // planes per volume tile
 constexpr int VOL_THREADS = 256;
 
 struct Mesh {
@@ -132,6 +162,7 @@ struct Mesh {
 };
 
 void build_topology(Mesh& M);
+const double* face_stencils(Mesh& M, int lam, hipStream_t s);
 
 // ------------------------------------------------------------ operators
 struct LevelOp {

@@ -1,0 +1,376 @@
+// Surrogate volume kernel for gfx950 (shared by the per-degree instantiation
+// units): y = L~ x, r = f - L~ x and the multicolour Gauss-Seidel update on
+// the volume primitives (Sec. 3.4 eq. ts; eq. iteration-scheme).
+//
+// Work decomposition: a workgroup owns one macro, a slab of R planes
+// k0 .. k0+R-1 and whole rows j0 .. j1-1 of plane k0's interior; each lane
+// owns a column (i, j) and marches up in k.  The surrogate polynomials are
+// reduced once per lane to 1D polynomials in zeta (the line-wise reduction of
+// Sec. 3.4) and evaluated with q FMAs per weight and step.  For every plane
+// p = k0-1 .. k0+R the rows j0-1 .. j1 form one contiguous range of the block
+// layout: the workgroup copies it into LDS with coalesced loads issued PF
+// planes ahead into registers, and every lane reads the 7 points of its
+// column from LDS into a rolling 3-plane register window.  All index
+// arithmetic advances incrementally from plane to plane.
+#pragma once
+
+#include "ts_internal.h"
+
+namespace ts {
+
+template <int Q>
+struct Basis {
+    static constexpr int MQ = (Q + 1) * (Q + 2) * (Q + 3) / 6;
+    int l[MQ], m[MQ], n[MQ];
+    constexpr Basis() : l(), m(), n() {
+        int c = 0;
+        for (int d = 0; d <= Q; d++)
+            for (int a = d; a >= 0; a--)
+                for (int b = d - a; b >= 0; b--) {
+                    l[c] = a;
+                    m[c] = b;
+                    n[c] = d - a - b;
+                    c++;
+                }
+    }
+};
+
+// position of the basis monomial xi^l eta^m zeta^n (degree d = l + m + n):
+// all terms of lower degree come first, then l descending, then m descending
+constexpr int basis_index(int l, int m, int n) {
+    const int d = l + m + n;
+    return d * (d + 1) * (d + 2) / 6 + (d - l) * (d - l + 1) / 2 + (d - l - m);
+}
+
+// position in the interior triangle of plane k0 -> (i, j); rows j = 1..Mr-1
+// hold Mr - j positions each (Mr = N - 1 - k0)
+__device__ __forceinline__ void pos_to_ij(int pos, int Mr, int& i, int& j) {
+    const double a = 2.0 * Mr - 1.0;
+    int J = (int)((a - sqrt(a * a - 8.0 * pos)) * 0.5);
+    if (J < 0) J = 0;
+    while (J > 0 && J * (2 * Mr - J - 1) / 2 > pos) J--;
+    while ((J + 1) * (2 * Mr - J - 2) / 2 <= pos) J++;
+    j = J + 1;
+    i = pos - J * (2 * Mr - J - 1) / 2 + 1;
+}
+
+// weights x neighbours: mc mw me ms mn mse mnw from plane k, bc be bn bnw
+// from k-1, tc tw ts tse from k+1
+template <typename T, typename W>
+__device__ __forceinline__ T off_sum(const W s[NW], const T pm[7], const T p0[7], const T pp[7]) {
+    T a = (T)s[1] * p0[1];
+    a += (T)s[2] * p0[2];
+    a += (T)s[3] * p0[3];
+    a += (T)s[4] * p0[4];
+    a += (T)s[5] * p0[5];
+    a += (T)s[6] * p0[6];
+    a += (T)s[7] * pm[0];
+    a += (T)s[8] * pm[2];
+    a += (T)s[9] * pm[4];
+    a += (T)s[10] * pm[6];
+    a += (T)s[11] * pp[0];
+    a += (T)s[12] * pp[1];
+    a += (T)s[13] * pp[3];
+    a += (T)s[14] * pp[5];
+    return a;
+}
+
+// XCD-aware block decode: workgroup b runs on XCD b % 8; all tiles of a macro
+// go to the same XCD so that the planes shared by neighbouring tiles stay in
+// that XCD's L2.
+__device__ __forceinline__ bool decode_block(int n_tiles, int nt, int& macro, int& tile) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7, loc = b >> 3;
+    const int grp = loc / n_tiles;
+    macro = grp * 8 + xcd;
+    tile = loc - grp * n_tiles;
+    return macro < nt;
+}
+
+// Surrogate: per lane, the 1D polynomials d_w(zeta) = sum_n d[w][n] zeta^n of
+// the column (i, j), from the 3D coefficients a_w (monomials of the centred,
+// scaled coordinates).  W is the arithmetic type of the weights.
+template <int Q, typename W, int CENTER>
+struct SurrogateW {
+    W d[NW][Q + 1];
+    W invN;
+    __device__ __forceinline__ void init_from(const float* __restrict__ cf,
+                                              const double* __restrict__ cd, int macro, int N,
+                                              int i, int j) {
+        constexpr int MQ = Basis<Q>::MQ;
+        if constexpr (sizeof(W) == 8)
+            init((const W*)cd + (size_t)macro * NW * MQ, N, i, j);
+        else
+            init((const W*)cf + (size_t)macro * NW * MQ, N, i, j);
+    }
+    __device__ __forceinline__ void init(const W* a, int N, int i, int j) {
+        constexpr Basis<Q> BS{};
+        constexpr int MQ = Basis<Q>::MQ;
+        invN = (W)1 / (W)N;
+        const W xi = (W)i * invN - (W)0.25, eta = (W)j * invN - (W)0.25;
+        // d_n = sum_l xi^l (sum_m a[l, m, n] eta^m): nested Horner, one FMA per
+        // basis term beyond the first of each n.  Weights are processed in
+        // groups of 3 so that only their coefficients are live in SGPRs.
+#pragma unroll
+        for (int g = 0; g < NW; g += 3) {
+#pragma unroll
+            for (int w = g; w < g + 3; w++) {
+#pragma unroll
+                for (int n = 0; n <= Q; n++) {
+                    W acc = (W)0;
+                    bool first = true;
+#pragma unroll
+                    for (int l = Q - n; l >= 0; l--) {
+                        W inner = (W)0;
+                        bool ifirst = true;
+#pragma unroll
+                        for (int m = Q - n - l; m >= 0; m--) {
+                            const W av = a[w * MQ + basis_index(l, m, n)];
+                            inner = ifirst ? av : inner * eta + av;
+                            ifirst = false;
+                        }
+                        acc = first ? inner : acc * xi + inner;
+                        first = false;
+                    }
+                    d[w][n] = acc;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        pin();
+    }
+    // Keep the column coefficients in VGPRs: some of them are wave-uniform
+    // (the top-degree ones), and held in SGPRs they overflow the scalar file.
+    __device__ __forceinline__ void pin() {
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+#pragma unroll
+            for (int n = 0; n <= Q; n++) asm volatile("" : "+v"(d[w][n]));
+    }
+    __device__ __forceinline__ void weights_z(W z, W s[NW]) const {
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            W v = d[w][Q];
+#pragma unroll
+            for (int n = Q - 1; n >= 0; n--) v = v * z + d[w][n];
+            s[w] = v;
+        }
+        if (CENTER == TS_CENTER_ROWSUM) {
+            W c = (W)0;
+#pragma unroll
+            for (int w = 1; w < NW; w++) c -= s[w];
+            s[0] = c;
+        }
+    }
+    __device__ __forceinline__ void weights(int k, W s[NW]) const {
+        const W z = (W)k * invN - (W)0.25;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            W v = d[w][Q];
+#pragma unroll
+            for (int n = Q - 1; n >= 0; n--) v = v * z + d[w][n];
+            s[w] = v;
+        }
+        if (CENTER == TS_CENTER_ROWSUM) {
+            W c = (W)0;
+#pragma unroll
+            for (int w = 1; w < NW; w++) c -= s[w];
+            s[0] = c;
+        }
+    }
+};
+
+// FP16 weight evaluation: the 1D column polynomials are evaluated in half
+// precision on coefficients pre-scaled by N (weights of order one), the
+// products and sums stay in FP32.
+template <int Q>
+struct SurrogateHalfW {
+    _Float16 d[NW][Q + 1];
+    float invN;
+    __device__ __forceinline__ void init_from(const float* __restrict__ cf,
+                                              const double* __restrict__ cd, int macro, int N,
+                                              int i, int j) {
+        constexpr Basis<Q> BS{};
+        constexpr int MQ = Basis<Q>::MQ;
+        (void)cd;
+        const float* a = cf + (size_t)macro * NW * MQ;
+        invN = 1.0f / (float)N;
+        const float xi = (float)i * invN - 0.25f, eta = (float)j * invN - 0.25f;
+        float xp[Q + 1], ep[Q + 1];
+        xp[0] = ep[0] = 1.0f;
+#pragma unroll
+        for (int q = 1; q <= Q; q++) {
+            xp[q] = xp[q - 1] * xi;
+            ep[q] = ep[q - 1] * eta;
+        }
+#pragma unroll
+        for (int g = 0; g < NW; g += 3) {
+#pragma unroll
+            for (int w = g; w < g + 3; w++) {
+                float t[Q + 1];
+#pragma unroll
+                for (int n = 0; n <= Q; n++) t[n] = 0.0f;
+#pragma unroll
+                for (int c = 0; c < MQ; c++) t[BS.n[c]] += a[w * MQ + c] * (xp[BS.l[c]] * ep[BS.m[c]]);
+#pragma unroll
+                for (int n = 0; n <= Q; n++) d[w][n] = (_Float16)t[n];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+#pragma unroll
+            for (int n = 0; n <= Q; n++) asm volatile("" : "+v"(d[w][n]));
+    }
+    // weights of order one (coefficients pre-scaled by N) evaluated in half
+    // precision, returned in float after scaling back by 1/N
+    __device__ __forceinline__ void weights_z(float zf, float s[NW]) const {
+        const _Float16 z = (_Float16)zf;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            _Float16 v = d[w][Q];
+#pragma unroll
+            for (int n = Q - 1; n >= 0; n--) v = v * z + d[w][n];
+            s[w] = (float)v * invN;
+        }
+    }
+};
+
+// Branch-free staging loads: entries past the plane's range read a valid
+// in-block address (their LDS copies are never used by a live step).
+template <typename T, int KPT>
+__device__ __forceinline__ void stage_load(const T* __restrict__ xm, int g0, int cnt, T r[KPT]) {
+    const int g = cnt > 0 ? g0 : 0;
+#pragma unroll
+    for (int s = 0; s < KPT; s++) {
+        const int e = (int)threadIdx.x + s * VOL_THREADS;
+        r[s] = xm[g + (e < cnt ? e : 0)];
+    }
+}
+
+// WP: weight provider (SurrogateW or SurrogateHalfW), T: vector type, W:
+// weight arithmetic type (float for the FP16 provider's products).
+template <class WP, typename T, typename W, int MODE, int R, int KPT>
+__global__ __launch_bounds__(VOL_THREADS)
+void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
+                const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
+                int nt, int N, int64_t B, int colour) {
+    constexpr int PF = TS_VOL_PF;
+    int macro, tile;
+    if (!decode_block(n_tiles, nt, macro, tile)) return;
+    const int4 td = tiles[tile];
+    const int k0 = td.x, j0 = td.y, j1 = td.z, i0 = td.w;
+    const int Mr = N - 1 - k0;
+    const int tid = (int)threadIdx.x;
+    // lanes without a column park at (1, j0): every index they form below
+    // stays inside the staged range, so reads need no guard
+    int i = 1, j = j0;
+    bool act;
+    if (i0 > 0) {
+        i = i0 + tid;
+        act = i <= Mr - j0;
+        if (!act) i = 1;
+    } else {
+        const int S0 = (j0 - 1) * (2 * Mr - j0) / 2;
+        const int S1 = (j1 - 1) * (2 * Mr - j1) / 2;
+        const int pos = S0 + tid;
+        act = pos < S1;
+        if (act) pos_to_ij(pos, Mr, i, j);
+    }
+    // number of live steps of this lane's column in the slab
+    const int nlive = act ? min(N - 1 - i - j, k0 + R - 1) - k0 + 1 : 0;
+    WP wp;
+    wp.init_from(coef_f, coef_d, macro, N, i, j);
+
+    __shared__ T buf[2][KPT * VOL_THREADS];
+    const size_t base = (size_t)macro * B;
+    const T* xm = x + base;
+    T* ym = y + base;
+    const T* fm = f ? f + base : nullptr;
+
+    // Incremental state.  Plane p has side A = N + 1 - p and po(p) points
+    // before it; po(p + 1) = po(p) + A (A + 1) / 2.  The staged range of
+    // plane p starts at row j0 - 1 (jb): g0 = po + jb A - jb (jb - 1) / 2.
+    const int jb = j0 - 1, jtri = jb * (jb - 1) / 2;
+    // lane: LDS index c of (i, j) = sum_{jb <= r < j} (A - r) + i; it drops by
+    // nb = j - jb from one plane to the next; qa = A - j drops by 1
+    const int nb = j - jb;
+    const int srow = (jb + j - 1) * nb / 2;
+    // global index of (i, j, k) advances by T(N + 1 - k) - j
+    int po_pf = (int)plane_off(N, k0 - 1);
+    T pf[PF][KPT];
+#pragma unroll
+    for (int d = 0; d < PF; d++) {
+        const int p = k0 - 1 + d;
+        const int A = N + 1 - p;
+        const int jl = min(j1, N - p);
+        const int nr = jl - jb + 1;
+        const int cnt = (p <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
+        stage_load<T, KPT>(xm, po_pf + jb * A - jtri, cnt, pf[d]);
+        po_pf += A * (A + 1) / 2;
+    }
+    int A0 = N + 2 - k0;                 // side of plane k0 - 1
+    int c = nb * A0 - srow + i;          // LDS index in plane k0 - 1
+    int qa = A0 - j;
+    // global index of (i, j, k0)
+    int idx = (int)plane_off(N, k0) + j * (N + 1 - k0) - j * (j - 1) / 2 + i;
+    const W invN = (W)1 / (W)N;
+    W z = (W)k0 * invN - (W)0.25;
+    int col = (i + 2 * j + 3 * k0) & 3;
+    T pm[7], p0[7], pp[7];
+#pragma unroll
+    for (int st = 0; st < R + 2; st++) {
+        const int p = k0 - 1 + st;
+        T* bb = buf[st & 1];
+#pragma unroll
+        for (int s2 = 0; s2 < KPT; s2++) bb[tid + s2 * VOL_THREADS] = pf[st % PF][s2];
+        __syncthreads();
+        if (st + PF <= R + 1) {
+            const int pq = p + PF;
+            const int A = N + 1 - pq;
+            const int jl = min(j1, N - pq);
+            const int nr = jl - jb + 1;
+            const int cnt = (pq <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
+            stage_load<T, KPT>(xm, po_pf + jb * A - jtri, cnt, pf[st % PF]);
+            po_pf += A * (A + 1) / 2;
+        }
+        // the 7 points of plane p: (i,j) c, (i-1,j), (i+1,j), (i,j-1) c-qa-1,
+        // (i+1,j-1), (i,j+1) c+qa, (i-1,j+1)
+        {
+            const int rs = c - qa - 1, rn = c + qa;
+            pp[0] = bb[c];
+            pp[1] = bb[c - 1];
+            pp[2] = bb[c + 1];
+            pp[3] = bb[rs];
+            pp[4] = bb[rn];
+            pp[5] = bb[rs + 1];
+            pp[6] = bb[rn - 1];
+        }
+        if (st >= 2) {
+            const int r = st - 2;  // step k = k0 + r
+            W sw[NW];
+            wp.weights_z(z, sw);
+            const T off = off_sum<T, W>(sw, pm, p0, pp);
+            const bool live = r < nlive;
+            if (MODE == 2) {
+                if (live && col == colour) ym[idx] = (fm[idx] - off) / (T)sw[0];
+                col = (col + 3) & 3;
+            } else {
+                const T v = (T)sw[0] * p0[0] + off;
+                if (live) ym[idx] = MODE == 0 ? v : fm[idx] - v;
+            }
+            const int Ak = N + 1 - (k0 + r);  // side of plane k
+            idx += Ak * (Ak + 1) / 2 - j;
+            z += invN;
+        }
+        c -= nb;
+        qa -= 1;
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            pm[q] = p0[q];
+            p0[q] = pp[q];
+        }
+    }
+}
+
+}  // namespace ts

@@ -227,6 +227,42 @@ Level& Mesh::level(int lam) {
     }
     L->if_free.upload(freel);
     L->n_if_free = (int)freel.size();
+    // face fast path: free nodes of interior faces (two copies)
+    {
+        std::vector<int> f2, rest;
+        std::vector<int4> c0, c1;
+        std::vector<int> f2pos(n_if, -1), restpos(n_if, -1);
+        for (int64_t n = 0; n < n_if; n++) {
+            const bool face = n >= nv + ne * (N - 1);
+            if (face && !(flag[n] & 1) && off[n + 1] - off[n] == 2) {
+                f2pos[n] = (int)f2.size();
+                f2.push_back((int)n);
+                c0.push_back(cp[off[n]]);
+                c1.push_back(cp[off[n] + 1]);
+            } else {
+                restpos[n] = (int)rest.size();
+                rest.push_back((int)n);
+            }
+        }
+        std::vector<int4> c01(c0);
+        c01.insert(c01.end(), c1.begin(), c1.end());
+        L->n_f2 = (int)f2.size();
+        L->f2_node.upload(f2);
+        L->f2_cp.upload(c01);
+        L->n_rest = (int)rest.size();
+        L->rest.upload(rest);
+        for (int p = 0; p < N_IF_PHASES; p++) {
+            std::vector<int> a, b;
+            for (int n : lists[p]) {
+                if (f2pos[n] >= 0) a.push_back(f2pos[n]);
+                else b.push_back(n);
+            }
+            L->f2_phase[p].upload(a);
+            L->n_f2_phase[p] = (int)a.size();
+            L->rest_phase[p].upload(b);
+            L->n_rest_phase[p] = (int)b.size();
+        }
+    }
 
     // volume tiles: planes k0 = 1, 1 + R, ... with chunks of positions of the
     // interior triangle of plane k0 (i, j >= 1, i + j <= N - 1 - k0)
@@ -238,6 +274,42 @@ Level& Mesh::level(int lam) {
     }
     L->tiles.upload(tiles);
     L->n_tiles = (int)tiles.size();
+    // LDS-staged tiles: whole rows of plane k0's interior up to 256
+    // positions, long rows split; the staged range of plane p covers rows
+    // j0-1 .. j1 of that plane
+    std::vector<int4> lt;
+    int64_t maxcnt = 1;
+    auto staged = [&](int k0, int j0, int j1) {
+        const int p = k0 - 1, A = N + 1 - p;
+        const int jl = std::min(j1, N - p);
+        int64_t c = 0;
+        for (int jj = j0 - 1; jj <= jl; jj++) c += A - jj;
+        return c;
+    };
+    for (int k0 = 1; k0 <= N - 3; k0 += VOL_R) {
+        const int Mr = N - 1 - k0;
+        int j = 1;
+        while (j <= Mr - 1) {
+            const int len = Mr - j;
+            if (len > VOL_THREADS) {
+                for (int i0 = 1; i0 <= len; i0 += VOL_THREADS) lt.push_back(make_int4(k0, j, j + 1, i0));
+                maxcnt = std::max(maxcnt, staged(k0, j, j + 1));
+                j++;
+                continue;
+            }
+            int j1 = j, tot = 0;
+            while (j1 <= Mr - 1 && tot + (Mr - j1) <= VOL_THREADS) {
+                tot += Mr - j1;
+                j1++;
+            }
+            lt.push_back(make_int4(k0, j, j1, 0));
+            maxcnt = std::max(maxcnt, staged(k0, j, j1));
+            j = j1;
+        }
+    }
+    L->lds_tiles.upload(lt);
+    L->n_lds_tiles = (int)lt.size();
+    L->lds_kpt = (int)((maxcnt + VOL_THREADS - 1) / VOL_THREADS);
     // all-slot tiles: every plane k = 0..N in chunks of 256 slots
     std::vector<int2> st;
     for (int k = 0; k <= N; k++) {

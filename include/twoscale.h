@@ -82,6 +82,12 @@ typedef struct {
     int q;        /* surrogate degree 1..4 (IPOLY: 2) */
     int sample_j; /* LSQP sampling set M_{m(l,j)}, m = min(l, max(1, j)) */
     int center;   /* TS_CENTER_POLY or TS_CENTER_ROWSUM */
+    double fallback_tol; /* selective surrogate (remark in Sec. 3.4): a macro
+                            keeps IFEM volume rows on a level if at one of the
+                            check points (1,1,1), (N-3,1,1), (1,N-3,1),
+                            (1,1,N-3), (N/4,N/4,N/4) its surrogate centre
+                            weight is <= 0 or differs from the exact one by
+                            more than fallback_tol times it; <= 0: never */
 } ts_op_params;
 
 typedef struct {
@@ -155,6 +161,9 @@ int ts_op_destroy(ts_op *op);
  * synchronous.  Import replaces them (checkpoint / shared coefficients). */
 int ts_op_coeffs_export(ts_op *op, int level, double *host, size_t n);
 int ts_op_coeffs_import(ts_op *op, int level, const double *host, size_t n);
+/* per-macro flags of one level (1: IFEM volume rows, selective surrogate);
+   n_macros host bytes, synchronous */
+int ts_op_macro_flags(ts_op *op, int level, unsigned char *host, size_t n);
 
 /* y = L x (Sec. 3.4 eq. ts): volume rows from the surrogate (IFEM rows for a
  * TS_IFEM operator or on level 2), lower-primitive rows by element-wise

@@ -94,6 +94,9 @@ def lib():
             "or_dirichlet_mask": (None, [P, I, P]),
             "or_fit_values": (I, [I, I, I, I, P, P]),
             "or_tets_at_list": (I, [I, I, I, I, P]),
+            "or_set_ifem_flags": (None, [P]),
+            "or_fallback_flags": (None, [P, I, I, P, D, P]),
+            "or_mg_set_flags": (None, [P, I, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -168,6 +171,12 @@ class Mesh:
         lib().or_ifem_stencil(self.h, N, t, i, j, k, _p(s))
         return s
 
+    def fallback_flags(self, N, q, coeffs, tol):
+        """Macros that keep IFEM rows on this level (selective surrogate)."""
+        f = np.zeros(self.nt, dtype=np.uint8)
+        lib().or_fallback_flags(self.h, N, q, _p(_f64(coeffs)), tol, _p(f))
+        return f
+
     def macro_fine_volume(self, N, t):
         return float(lib().or_macro_fine_volume(self.h, N, t))
 
@@ -180,14 +189,16 @@ class Mesh:
         return c
 
     # --- operator ---------------------------------------------------------
-    def apply(self, N, x, kind=IFEM, q=2, center=0, coeffs=None):
+    def apply(self, N, x, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
+        _set_flags(flags)
         x = _f64(x)
         y = np.zeros_like(x)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
         lib().or_apply(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(x), _p(y))
         return y
 
-    def apply_rows(self, N, x, rows, kind=IFEM, q=2, center=0, coeffs=None):
+    def apply_rows(self, N, x, rows, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
+        _set_flags(flags)
         x = _f64(x)
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         y = np.zeros(rows.shape[0])
@@ -196,14 +207,16 @@ class Mesh:
                             rows.shape[0], _p(y))
         return y
 
-    def residual(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None):
+    def residual(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
+        _set_flags(flags)
         f, u = _f64(f), _f64(u)
         r = np.zeros_like(u)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
         lib().or_residual(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(f), _p(u), _p(r))
         return r
 
-    def gs_sweep(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None):
+    def gs_sweep(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
+        _set_flags(flags)
         f = _f64(f)
         u = np.array(u, dtype=np.float64, copy=True)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
@@ -258,7 +271,8 @@ class Mesh:
 class Multigrid:
     """V(nu1, nu2) cycle of the oracle on levels N = 2^lam, lam0..lamL."""
 
-    def __init__(self, mesh, lam0, lamL, kind=IFEM, q=2, center=0, coeffs=None, nu1=3, nu2=3):
+    def __init__(self, mesh, lam0, lamL, kind=IFEM, q=2, center=0, coeffs=None, nu1=3, nu2=3,
+                 flags=None):
         self.mesh = mesh
         self.lam0, self.lamL = lam0, lamL
         nl = lamL - lam0 + 1
@@ -274,6 +288,12 @@ class Multigrid:
         self._arr = arr
         self.h = lib().or_mg_new(mesh.h, lam0, lamL, 1 if kind else 0, q, center, nu1, nu2,
                                  C.cast(arr, C.c_void_p))
+        if flags is not None:
+            for l in range(nl):
+                if flags[l] is not None:
+                    a = np.ascontiguousarray(flags[l], dtype=np.uint8)
+                    self._keep.append(a)
+                    lib().or_mg_set_flags(self.h, lam0 + l, _p(a))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -293,6 +313,20 @@ class Multigrid:
         c = lib().or_solve(self.h, _p(f), _p(u), rtol, max_cycles, _p(hist))
         n = c if c >= 0 else max_cycles
         return u, int(c), hist[: n + 1]
+
+
+_flag_keep = [None]
+
+
+def _set_flags(flags):
+    """Per-macro IFEM fallback flags for the next operator call (None: none)."""
+    if flags is None:
+        _flag_keep[0] = None
+        lib().or_set_ifem_flags(None)
+    else:
+        a = np.ascontiguousarray(flags, dtype=np.uint8)
+        _flag_keep[0] = a
+        lib().or_set_ifem_flags(_p(a))
 
 
 def num_coeffs(q):

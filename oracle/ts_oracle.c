@@ -740,6 +740,7 @@ int or_fit(const or_mesh *M, int N, int method, int q, int jsamp, double *coeffs
 typedef struct {
     int kind, q, center;
     const double *coeffs;
+    const unsigned char *ifem; /* per macro: 1 = IFEM rows on the volume (NULL: none) */
 } or_op;
 
 static int64_t vol_base(const or_mesh *M, int N) {
@@ -809,7 +810,7 @@ static void row_surrogate(const or_mesh *M, int N, const or_op *op, int64_t t, i
 /* row of the interior node (i, j, k) of macro t under op */
 static void row_volume(const or_mesh *M, int N, const or_op *op, int64_t t, int i, int j,
                        int k, const double *x, double *diag, double *off) {
-    if (op->kind == 1) {
+    if (op->kind == 1 && !(op->ifem && op->ifem[t])) {
         row_surrogate(M, N, op, t, i, j, k, x, diag, off);
     } else {
         int64_t ct[1] = {t};
@@ -886,10 +887,15 @@ static void zero_dirichlet(const or_mesh *M, int N, double *y) {
         if (or_is_dirichlet(M, N, u)) y[u] = 0;
 }
 
+/* Per-macro IFEM fallback flags used by the operator entry points below
+   (set with or_set_ifem_flags; NULL: surrogate rows on every macro). */
+static const unsigned char *g_flags = NULL;
+void or_set_ifem_flags(const unsigned char *flags) { g_flags = flags; }
+
 /* y = L x over the free rows; Dirichlet rows of y are set to 0. */
 void or_apply(const or_mesh *M, int N, int kind, int q, int center,
               const double *coeffs, const double *x, double *y) {
-    or_op op = {kind, q, center, coeffs};
+    or_op op = {kind, q, center, coeffs, g_flags};
     rows_ctx c = {x, NULL, y};
     zero_dirichlet(M, N, y);
     for_rows(M, N, &op, x, -1, cb_apply, &c);
@@ -899,7 +905,7 @@ void or_apply(const or_mesh *M, int N, int kind, int q, int center,
 void or_apply_rows(const or_mesh *M, int N, int kind, int q, int center,
                    const double *coeffs, const double *x, const int64_t *rows,
                    int64_t nrows, double *y) {
-    or_op op = {kind, q, center, coeffs};
+    or_op op = {kind, q, center, coeffs, g_flags};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < nrows; r++) {
         int64_t u = rows[r];
@@ -913,7 +919,7 @@ void or_apply_rows(const or_mesh *M, int N, int kind, int q, int center,
 /* r = f - L u on the free rows, 0 on Dirichlet rows. */
 void or_residual(const or_mesh *M, int N, int kind, int q, int center,
                  const double *coeffs, const double *f, const double *u, double *r) {
-    or_op op = {kind, q, center, coeffs};
+    or_op op = {kind, q, center, coeffs, g_flags};
     rows_ctx c = {u, f, r};
     zero_dirichlet(M, N, r);
     for_rows(M, N, &op, u, -1, cb_residual, &c);
@@ -924,7 +930,7 @@ void or_residual(const or_mesh *M, int N, int kind, int q, int center,
    of that phase. */
 void or_gs_sweep(const or_mesh *M, int N, int kind, int q, int center,
                  const double *coeffs, const double *f, double *u) {
-    or_op op = {kind, q, center, coeffs};
+    or_op op = {kind, q, center, coeffs, g_flags};
     int64_t nu = or_num_unique(M, N);
     int64_t vb = vol_base(M, N);
     int64_t V = n_vol_int(N);
@@ -1110,6 +1116,7 @@ typedef struct {
     const or_mesh *M;
     int lam0, lamL, kind, q, center, nu1, nu2;
     const double **coeffs;
+    const unsigned char **flags;
     or_coarse *coarse;
 } or_mg;
 
@@ -1120,15 +1127,21 @@ or_mg *or_mg_new(const or_mesh *M, int lam0, int lamL, int kind, int q, int cent
     G->center = center; G->nu1 = nu1; G->nu2 = nu2;
     int nl = lamL - lam0 + 1;
     G->coeffs = calloc(nl, sizeof(double *));
+    G->flags = calloc(nl, sizeof(unsigned char *));
     for (int l = 0; l < nl; l++) G->coeffs[l] = coeffs ? coeffs[l] : NULL;
     G->coarse = or_coarse_new(M, 1 << lam0);
     return G;
+}
+
+void or_mg_set_flags(or_mg *G, int lam, const unsigned char *flags) {
+    G->flags[lam - G->lam0] = flags;
 }
 
 void or_mg_free(or_mg *G) {
     if (!G) return;
     or_coarse_free(G->coarse);
     free(G->coeffs);
+    free(G->flags);
     free(G);
 }
 
@@ -1141,6 +1154,7 @@ static void vcycle_rec(const or_mg *G, int lam, const double *f, double *u) {
     }
     int kind = G->kind;
     const double *cf = G->coeffs[lam - G->lam0];
+    or_set_ifem_flags(G->flags[lam - G->lam0]);
     for (int s = 0; s < G->nu1; s++) or_gs_sweep(M, N, kind, G->q, G->center, cf, f, u);
     int64_t nf = or_num_unique(M, N), nc = or_num_unique(M, N / 2);
     double *r = malloc(sizeof(double) * nf);
@@ -1150,6 +1164,7 @@ static void vcycle_rec(const or_mg *G, int lam, const double *f, double *u) {
     or_residual(M, N, kind, G->q, G->center, cf, f, u, r);
     or_restrict(M, N, r, fc);
     vcycle_rec(G, lam - 1, fc, uc);
+    or_set_ifem_flags(G->flags[lam - G->lam0]);
     or_prolongate(M, N, uc, e);
     for (int64_t v = 0; v < nf; v++) u[v] += e[v];
     for (int s = 0; s < G->nu2; s++) or_gs_sweep(M, N, kind, G->q, G->center, cf, f, u);
@@ -1180,12 +1195,14 @@ int or_solve(const or_mg *G, const double *f, double *u, double rtol,
     double *r = malloc(sizeof(double) * nu);
     const double *cf = G->coeffs[G->lamL - G->lam0];
     double nf = or_norm_free(M, N, f);
+    or_set_ifem_flags(G->flags[G->lamL - G->lam0]);
     or_residual(M, N, G->kind, G->q, G->center, cf, f, u, r);
     double rel = or_norm_free(M, N, r) / nf;
     if (hist) hist[0] = rel;
     int c = 0;
     while (rel > rtol && c < max_cycles) {
         or_vcycle(G, f, u);
+        or_set_ifem_flags(G->flags[G->lamL - G->lam0]);
         or_residual(M, N, G->kind, G->q, G->center, cf, f, u, r);
         rel = or_norm_free(M, N, r) / nf;
         c++;
@@ -1379,4 +1396,26 @@ int or_tets_at_list(int N, int i, int j, int k, int *out) {
     int n = tets_at(N, p, tl);
     memcpy(out, tl, sizeof(int) * 12 * n);
     return n;
+}
+
+/* Selective surrogate (remark in Sec. 3.4: the surrogate can be switched off
+   per macro depending on its shape): a macro keeps IFEM rows on this level if
+   at any of the check points (1,1,1), (N-3,1,1), (1,N-3,1), (1,1,N-3) and
+   (N/4,N/4,N/4) the surrogate centre weight is not positive or differs from
+   the exact one by more than tol times the exact one.  tol <= 0 disables the
+   check (all flags 0). */
+void or_fallback_flags(const or_mesh *M, int N, int q, const double *coeffs, double tol,
+                       unsigned char *flags) {
+    int mq = or_num_coeffs(q);
+    for (int64_t t = 0; t < M->nt; t++) {
+        flags[t] = 0;
+        if (tol <= 0) continue;
+        int P[5][3] = {{1, 1, 1}, {N - 3, 1, 1}, {1, N - 3, 1}, {1, 1, N - 3}, {N / 4, N / 4, N / 4}};
+        for (int c = 0; c < 5; c++) {
+            double s[NW];
+            or_ifem_stencil(M, N, t, P[c][0], P[c][1], P[c][2], s);
+            double e = or_poly_eval(q, N, coeffs + t * NW * mq, P[c][0], P[c][1], P[c][2]);
+            if (!(e > 0) || fabs(e - s[0]) > tol * s[0]) flags[t] = 1;
+        }
+    }
 }

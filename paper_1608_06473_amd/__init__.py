@@ -46,7 +46,8 @@ class ts_layout_info(C.Structure):
 
 
 class ts_op_params(C.Structure):
-    _fields_ = [("method", C.c_int), ("q", C.c_int), ("sample_j", C.c_int), ("center", C.c_int)]
+    _fields_ = [("method", C.c_int), ("q", C.c_int), ("sample_j", C.c_int), ("center", C.c_int),
+                ("fallback_tol", C.c_double)]
 
 
 class ts_solve_params(C.Structure):
@@ -72,6 +73,7 @@ _SIGS = {
     "ts_op_destroy": (C.c_int, [C.c_void_p]),
     "ts_op_coeffs_export": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     "ts_op_coeffs_import": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
+    "ts_op_macro_flags": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     "ts_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_apply_volume": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -177,8 +179,8 @@ def ts_rhs(mesh, level, kind, params, f, stream=None):
 
 
 def ts_op_create(mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 stream=None):
-    p = ts_op_params(method, q, sample_j, center)
+                 fallback_tol=0.0, stream=None):
+    p = ts_op_params(method, q, sample_j, center, fallback_tol)
     h = C.c_void_p()
     _check(lib().ts_op_create(mesh, max_level, C.byref(p), _stream(stream), C.byref(h)))
     return h
@@ -197,6 +199,12 @@ def ts_op_coeffs_export(op, level, out):
 def ts_op_coeffs_import(op, level, coeffs):
     c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1)
     return _check(lib().ts_op_coeffs_import(op, level, _ptr(c), c.size))
+
+
+def ts_op_macro_flags(op, level, out):
+    out = np.ascontiguousarray(out, dtype=np.uint8)
+    _check(lib().ts_op_macro_flags(op, level, _ptr(out), out.size))
+    return out
 
 
 def ts_apply(op, level, dtype, x, y, stream=None):
@@ -312,11 +320,16 @@ class Mesh:
 class Operator:
     """Owning wrapper of a ts_op handle (keeps its mesh alive)."""
 
-    def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY):
+    def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
+                 fallback_tol=0.0):
         self.mesh = mesh
         self.method, self.q = method, q
         self.max_level = max_level
-        self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center)
+        self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol)
+
+    def macro_flags(self, level):
+        """1 for macros whose volume rows stay IFEM on this level."""
+        return ts_op_macro_flags(self.h, level, np.zeros(self.mesh.tet.shape[0], np.uint8))
 
     def coeffs(self, level):
         nt = self.mesh.tet.shape[0]

@@ -503,6 +503,39 @@ __global__ __launch_bounds__(128) void k_sample(double* __restrict__ Bout, const
     for (int w = 0; w < NW; w++) o[w] = st[w];
 }
 
+__device__ __forceinline__ int basis_row(int q, int N, int i, int j, int k, double* row);
+
+// Selective surrogate check (remark in Sec. 3.4): one thread per macro
+// compares the exact centre weight with the surrogate's centre polynomial at
+// five interior points near the macro's vertices and centre.
+__global__ __launch_bounds__(64) void k_fallback_check(unsigned char* __restrict__ flags,
+                                                       const MacroGeom* __restrict__ geom,
+                                                       const double* __restrict__ coef, int nt,
+                                                       int N, int q, int mq, double tol) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nt) return;
+    const int P[5][3] = {{1, 1, 1}, {N - 3, 1, 1}, {1, N - 3, 1}, {1, 1, N - 3}, {N / 4, N / 4, N / 4}};
+    const double* c0 = coef + (size_t)m * NW * mq;  // direction 0 (centre)
+    unsigned char bad = 0;
+    for (int c = 0; c < 5; c++) {
+        double st[NW], row[35];
+        ifem_partial_stencil(geom[m], N, P[c][0], P[c][1], P[c][2], st);
+        basis_row(q, N, P[c][0], P[c][1], P[c][2], row);
+        double e = 0.0;
+        for (int a = 0; a < mq; a++) e += c0[a] * row[a];
+        if (!(e > 0.0) || fabs(e - st[0]) > tol * st[0]) bad = 1;
+    }
+    flags[m] = bad;
+}
+
+void launch_fallback_check(const Mesh& M, int lam, int q, const double* coef, double tol,
+                           unsigned char* flags, hipStream_t s) {
+    const int nt = (int)M.nt, mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    k_fallback_check<<<(nt + 63) / 64, 64, 0, s>>>(flags, M.d_geom.p, coef, nt, 1 << lam, q, mq,
+                                                   tol);
+    TS_HIP(hipGetLastError());
+}
+
 void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s) {
     const dim3 g((npts + 127) / 128, (unsigned)M.nt);
     k_sample<<<g, 128, 0, s>>>(B, M.d_geom.p, pts, npts, 1 << lam);

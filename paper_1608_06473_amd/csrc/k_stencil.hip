@@ -88,9 +88,10 @@ __device__ __forceinline__ void volume_body(const T* xm, T* ym, const T* fm, WP&
 template <typename T, int MODE, int R>
 __global__ __launch_bounds__(VOL_THREADS) void k_ifem_volume(
     const T* x, T* y, const T* __restrict__ f, const MacroGeom* __restrict__ geom,
-    const int2* __restrict__ tiles, int n_tiles, int nt, int N, int64_t B, int colour) {
+    const int2* __restrict__ tiles, int n_tiles, int nt, const int* __restrict__ mlist, int N,
+    int64_t B, int colour) {
     int macro, tile;
-    if (!decode_block(n_tiles, nt, macro, tile)) return;
+    if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
     const int2 td = tiles[tile];
     const int k0 = td.x, Mr = N - 1 - k0;
     const int pos = td.y + (int)threadIdx.x;
@@ -298,6 +299,10 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     const Level& L = const_cast<Mesh&>(M).level(lam);
     const LevelOp& lo = *op->lv.at(lam);
     const int nt = (int)M.nt, q = op->p.q, c = op->p.center;
+    if (lo.n_ifem)  // selective surrogate: these macros keep IFEM rows
+        launch_ifem_volume(op, lam, dtype == TS_F16W ? TS_F32 : dtype, mode, x, y, f, colour, s,
+                           lo.ifem_list.p, lo.n_ifem);
+    if (lo.n_sur == 0) return;
     const int kpt = L.lds_kpt <= 2 ? 2 : L.lds_kpt <= 4 ? 4 : 8;
     TS_REQUIRE(L.lds_kpt <= 8, TS_EINVAL, "level too large for the surrogate volume kernel");
 #define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s)
@@ -322,29 +327,30 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
 
 template <typename T>
 static void run_ifem_volume(const Mesh& M, const Level& L, int mode, const void* x, void* y,
-                            const void* f, int colour, hipStream_t s) {
-    const int nt = (int)M.nt;
+                            const void* f, int colour, hipStream_t s, const int* ml, int nt) {
     const dim3 grid(grid_volume(L, nt)), blk(VOL_THREADS);
     if (grid.x == 0) return;
     const T* xp = (const T*)x;
     T* yp = (T*)y;
     const T* fp = (const T*)f;
     if (mode == 0)
-        k_ifem_volume<T, 0, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, L.N, L.B, colour);
+        k_ifem_volume<T, 0, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
     else if (mode == 1)
-        k_ifem_volume<T, 1, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, L.N, L.B, colour);
+        k_ifem_volume<T, 1, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
     else
-        k_ifem_volume<T, 2, VOL_R><<<grid, blk, 0, s>>>(yp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, L.N, L.B, colour);
+        k_ifem_volume<T, 2, VOL_R><<<grid, blk, 0, s>>>(yp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
 }
 
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                        const void* f, int colour, hipStream_t s) {
+                        const void* f, int colour, hipStream_t s, const int* mlist, int n_list) {
     const Mesh& M = op->mesh->m;
     const Level& L = const_cast<Mesh&>(M).level(lam);
+    const int nt = n_list >= 0 ? n_list : (int)M.nt;
+    if (nt == 0) return;
     if (dtype == TS_F64)
-        run_ifem_volume<double>(M, L, mode, x, y, f, colour, s);
+        run_ifem_volume<double>(M, L, mode, x, y, f, colour, s, mlist, nt);
     else
-        run_ifem_volume<float>(M, L, mode, x, y, f, colour, s);
+        run_ifem_volume<float>(M, L, mode, x, y, f, colour, s, mlist, nt);
     TS_HIP(hipGetLastError());
 }
 

@@ -15,19 +15,19 @@
 namespace ts {
 
 template <class WP, typename T, typename W>
-static void run(const Level& L, int nt, const float* cf, const double* cd, int mode,
-                const void* x, void* y, const void* f, int colour, hipStream_t s) {
+static void run(const Level& L, int nt, const int* ml, const float* cf, const double* cd,
+                int mode, const void* x, void* y, const void* f, int colour, hipStream_t s) {
     const dim3 grid((unsigned)(((nt + 7) / 8) * 8 * L.n_lds_tiles)), blk(VOL_THREADS);
     if (grid.x == 0 || L.n_lds_tiles == 0) return;
     const T* xp = (const T*)x;
     T* yp = (T*)y;
     const T* fp = (const T*)f;
     if (mode == 0)
-        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.N, L.B, colour);
     else if (mode == 1)
-        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.N, L.B, colour);
     else
-        k_surr_lds<WP, T, W, 2, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(yp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 2, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(yp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.N, L.B, colour);
 }
 
 // dtype TS_F64: FP64 vectors and weights; TS_F32: FP32; TS_F16W: FP32 vectors
@@ -36,18 +36,20 @@ void TS_CAT(launch_surr_q, TS_Q, _k, TS_KPT)(const Level& L, int nt, const Level
                                               int center, int mode, const void* x, void* y,
                                               const void* f, int colour, hipStream_t s) {
     constexpr int Q = TS_Q;
+    const int* ml = lo.sur_list.p;
+    nt = lo.n_sur;
     if (dtype == TS_F64) {
         if (center == TS_CENTER_POLY)
-            run<SurrogateW<Q, double, TS_CENTER_POLY>, double, double>(L, nt, nullptr, lo.coef64.p, mode, x, y, f, colour, s);
+            run<SurrogateW<Q, double, TS_CENTER_POLY>, double, double>(L, nt, ml, nullptr, lo.coef64.p, mode, x, y, f, colour, s);
         else
-            run<SurrogateW<Q, double, TS_CENTER_ROWSUM>, double, double>(L, nt, nullptr, lo.coef64.p, mode, x, y, f, colour, s);
+            run<SurrogateW<Q, double, TS_CENTER_ROWSUM>, double, double>(L, nt, ml, nullptr, lo.coef64.p, mode, x, y, f, colour, s);
     } else if (dtype == TS_F32) {
         if (center == TS_CENTER_POLY)
-            run<SurrogateW<Q, float, TS_CENTER_POLY>, float, float>(L, nt, lo.coef32.p, nullptr, mode, x, y, f, colour, s);
+            run<SurrogateW<Q, float, TS_CENTER_POLY>, float, float>(L, nt, ml, lo.coef32.p, nullptr, mode, x, y, f, colour, s);
         else
-            run<SurrogateW<Q, float, TS_CENTER_ROWSUM>, float, float>(L, nt, lo.coef32.p, nullptr, mode, x, y, f, colour, s);
+            run<SurrogateW<Q, float, TS_CENTER_ROWSUM>, float, float>(L, nt, ml, lo.coef32.p, nullptr, mode, x, y, f, colour, s);
     } else {
-        run<SurrogateHalfW<Q>, float, float>(L, nt, lo.coef16s.p, nullptr, mode, x, y, f, colour, s);
+        run<SurrogateHalfW<Q>, float, float>(L, nt, ml, lo.coef16s.p, nullptr, mode, x, y, f, colour, s);
     }
 }
 

@@ -69,6 +69,27 @@ static bool uses_surrogate(const ts_op* op, int lam) {
     return op->p.method != TS_IFEM && lam >= 3 && op->lv.count(lam) && op->lv.at(lam)->has_coef;
 }
 
+// Per-macro split of the volume rows (selective surrogate): run the check on
+// the device coefficients, then upload the surrogate and IFEM macro lists.
+static void split_macros(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
+    const Mesh& M = op->mesh->m;
+    const int nt = (int)M.nt;
+    lo.flags.assign(nt, 0);
+    if (op->p.fallback_tol > 0) {
+        DBuf<unsigned char> d;
+        d.alloc(nt);
+        launch_fallback_check(M, lam, op->p.q, lo.coef64.p, op->p.fallback_tol, d.p, s);
+        TS_HIP(hipMemcpyAsync(lo.flags.data(), d.p, nt, hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int> sur, ifem;
+    for (int t = 0; t < nt; t++) (lo.flags[t] ? ifem : sur).push_back(t);
+    lo.n_sur = (int)sur.size();
+    lo.n_ifem = (int)ifem.size();
+    if (lo.n_sur) lo.sur_list.upload(sur); else lo.sur_list.reset();
+    if (lo.n_ifem) lo.ifem_list.upload(ifem); else lo.ifem_list.reset();
+}
+
 static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vector<double>& h) {
     const int N = 1 << lam;
     std::vector<float> f32(h.size()), f16s(h.size());
@@ -104,6 +125,7 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         TS_HIP(hipStreamSynchronize(s));
         for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite surrogate coefficient");
         upload_coef_variants(op, *lo, lam, h);
+        split_macros(op, *lo, lam, s);
     }
     op->lv[lam] = std::move(lo);
 }
@@ -395,6 +417,7 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             TS_REQUIRE(p->method != TS_IPOLY || p->q == 2, TS_EINVAL, "IPOLY is defined for q = 2");
             TS_REQUIRE(p->center == TS_CENTER_POLY || p->center == TS_CENTER_ROWSUM, TS_EINVAL,
                        "bad centre mode");
+            TS_REQUIRE(!std::isnan(p->fallback_tol), TS_EINVAL, "fallback_tol is NaN");
         }
         auto* op = new ts_op();
         try {
@@ -439,6 +462,20 @@ int ts_op_coeffs_import(ts_op* op, int level, const double* host, size_t n) {
         LevelOp& lo = *op->lv[level];
         TS_HIP(hipMemcpy(lo.coef64.p, h.data(), need * sizeof(double), hipMemcpyHostToDevice));
         upload_coef_variants(op, lo, level, h);
+        split_macros(op, lo, level, nullptr);
+    });
+}
+
+int ts_op_macro_flags(ts_op* op, int level, unsigned char* host, size_t n) {
+    return guarded([&] {
+        TS_REQUIRE(op && host, TS_EINVAL, "null argument");
+        TS_REQUIRE(level >= 2 && level <= op->max_level, TS_EINVAL,
+                   "level outside the operator's range");
+        const int64_t nt = op->mesh->m.nt;
+        TS_REQUIRE(n >= (size_t)nt, TS_EINVAL, "buffer too small");
+        const LevelOp& lo = *op->lv.at(level);
+        for (int64_t t = 0; t < nt; t++)
+            host[t] = uses_surrogate(op, level) && !lo.flags.empty() ? lo.flags[t] : 0;
     });
 }
 

@@ -170,6 +170,10 @@ struct LevelOp {
     DBuf<double> coef64;   // [nt][15][mq]
     DBuf<float> coef32;
     DBuf<float> coef16s;   // FP16-weight variant: coefficients pre-scaled by N
+    // selective surrogate: macros with surrogate volume rows / with IFEM rows
+    std::vector<unsigned char> flags;
+    DBuf<int> sur_list, ifem_list;
+    int n_sur = 0, n_ifem = 0;
     bool has_coef = false;
 };
 
@@ -199,7 +203,10 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
 void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
                           void* u, hipStream_t s);
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                        const void* f, int colour, hipStream_t s);
+                        const void* f, int colour, hipStream_t s, const int* mlist = nullptr,
+                        int n_list = -1);
+void launch_fallback_check(const Mesh& M, int lam, int q, const double* coef, double tol,
+                           unsigned char* flags, hipStream_t s);
 void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* rc, hipStream_t s);
 void launch_prolongate_add(const Mesh& M, int lam_f, int dtype, const void* uc, void* uf,
                            hipStream_t s);

@@ -78,13 +78,17 @@ __device__ __forceinline__ T off_sum(const W s[NW], const T pm[7], const T p0[7]
 // XCD-aware block decode: workgroup b runs on XCD b % 8; all tiles of a macro
 // go to the same XCD so that the planes shared by neighbouring tiles stay in
 // that XCD's L2.
-__device__ __forceinline__ bool decode_block(int n_tiles, int nt, int& macro, int& tile) {
+// mlist (optional) maps the nt list positions to macro ids.
+__device__ __forceinline__ bool decode_block(int n_tiles, int nt, int& macro, int& tile,
+                                             const int* __restrict__ mlist = nullptr) {
     const int b = blockIdx.x;
     const int xcd = b & 7, loc = b >> 3;
     const int grp = loc / n_tiles;
     macro = grp * 8 + xcd;
     tile = loc - grp * n_tiles;
-    return macro < nt;
+    if (macro >= nt) return false;
+    if (mlist) macro = mlist[macro];
+    return true;
 }
 
 // Surrogate: per lane, the 1D polynomials d_w(zeta) = sum_n d[w][n] zeta^n of
@@ -254,10 +258,10 @@ template <class WP, typename T, typename W, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS)
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
-                int nt, int N, int64_t B, int colour) {
+                int nt, const int* __restrict__ mlist, int N, int64_t B, int colour) {
     constexpr int PF = TS_VOL_PF;
     int macro, tile;
-    if (!decode_block(n_tiles, nt, macro, tile)) return;
+    if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
     const int4 td = tiles[tile];
     const int k0 = td.x, j0 = td.y, j1 = td.z, i0 = td.w;
     const int Mr = N - 1 - k0;

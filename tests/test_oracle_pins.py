@@ -438,3 +438,68 @@ def test_ifem_error_is_order_h2(orc):
         errs.append(np.sqrt((V * (u - ue) ** 2).sum()))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.0 < r2 < 5.0 and r2 > r1 * 0.8
+
+
+# ---------------------------------------------------------------------------
+# selective surrogate (remark in Sec. 3.4): per-macro IFEM fallback
+
+
+def _check_points(N):
+    return [(1, 1, 1), (N - 3, 1, 1), (1, N - 3, 1), (1, 1, N - 3), (N // 4, N // 4, N // 4)]
+
+
+def test_fallback_rule_vs_global_assembly(orc):
+    """The fallback check compares against the diagonal of the independent
+    global assembly; a tolerance inside the spread of the deviations splits
+    the macros, and a planted negative centre weight is always caught."""
+    from oracle.brute import Brute, local_nodes
+    v, t = inputs.shell36()
+    N, q = 16, 2
+    M = orc.Mesh(v, t)
+    c = M.fit(N, orc.LSQP, q=q, jsamp=2)
+    B = Brute(v, t, N)
+    loc = {tuple(p): n for n, p in enumerate(local_nodes(N))}
+    diag = B.A.diagonal()
+    dev = np.zeros(len(t))
+    for m in range(len(t)):
+        for (i, j, k) in _check_points(N):
+            e = diag[B.slot_node[m * B.nloc + loc[(i, j, k)]]]
+            s = orc.poly_eval(q, N, c[m, 0], i, j, k)
+            assert s > 0
+            dev[m] = max(dev[m], abs(s - e) / e)
+    srt = np.sort(dev)
+    g = np.argmax(np.diff(srt)[8:28]) + 8          # widest gap near the middle
+    tol = 0.5 * (srt[g] + srt[g + 1])
+    want = (dev > tol).astype(np.uint8)
+    assert 0 < want.sum() < len(t)
+    assert np.array_equal(M.fallback_flags(N, q, c, tol), want)
+    assert not M.fallback_flags(N, q, c, 0.0).any()         # disabled
+    assert not M.fallback_flags(N, q, c, 10.0 * srt[-1]).any()
+    c2 = c.copy()
+    c2[5, 0, 0] -= 10.0 * abs(c2[5, 0]).sum()                 # centre weight < 0
+    f2 = M.fallback_flags(N, q, c2, 1e6)
+    assert f2[5] == 1 and f2.sum() == 1
+
+
+def test_fallback_rows_are_ifem_rows(orc):
+    """With the flags set, the volume rows of flagged macros are IFEM rows and
+    all others keep the surrogate; all flags set gives the IFEM operator."""
+    v, t = inputs.shell36()
+    N, q = 8, 2
+    M = orc.Mesh(v, t)
+    c = M.fit(N, orc.LSQP, q=q, jsamp=2)
+    x = inputs.uniform(M.num_unique(N), 7)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    ys = M.apply(N, x, kind=orc.LSQP, q=q, coeffs=c)
+    ya = M.apply(N, x, kind=orc.LSQP, q=q, coeffs=c, flags=np.ones(len(t), np.uint8))
+    assert np.array_equal(ya, yi)
+    y0 = M.apply(N, x, kind=orc.LSQP, q=q, coeffs=c, flags=np.zeros(len(t), np.uint8))
+    assert np.array_equal(y0, ys)
+    fl = (np.arange(len(t)) % 3 == 0).astype(np.uint8)
+    ym = M.apply(N, x, kind=orc.LSQP, q=q, coeffs=c, flags=fl)
+    nvol = (N - 1) * (N - 2) * (N - 3) // 6
+    nlow = M.num_unique(N) - len(t) * nvol
+    for m in range(len(t)):
+        sl = slice(nlow + m * nvol, nlow + (m + 1) * nvol)
+        assert np.array_equal(ym[sl], (yi if fl[m] else ys)[sl])
+    assert np.array_equal(ym[:nlow], ys[:nlow])

@@ -136,42 +136,35 @@ __device__ __forceinline__ void nbr_index(int base, int A, int j, int o[NW]) {
     o[14] = tp - (A - j) + 1;
 }
 
-// General path: one thread per listed face/edge/vertex node, summing over the
-// node's copies the element-wise partial stencil of each adjacent macro,
-// assembled on the fly.  MODE 0: y = L x; 1: y = f - L x, written to every
-// copy; 2: Gauss-Seidel value (f - off) / diag into tmp[t].
+// General path: one thread per listed free face/edge/vertex node, summing
+// over the node's copies the stored element-wise partial stencil of each
+// adjacent macro.  MODE 0: y = L x; 1: y = f - L x, written to every copy;
+// 2: Gauss-Seidel value (f - off) / diag into tmp[t].
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_iface(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
-    const int* __restrict__ off, const int4* __restrict__ cp,
-    const unsigned char* __restrict__ flag, const int* __restrict__ list, int n,
-    const MacroGeom* __restrict__ geom, int N, int64_t B, double* __restrict__ tmp) {
+    const int* __restrict__ off, const int4* __restrict__ cp, const int* __restrict__ rc_base,
+    const double* __restrict__ sten, int n_rc, const int* __restrict__ list, int n, int N,
+    int64_t B, double* __restrict__ tmp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int node = list ? list[t] : t;
+    const int node = list[t];
     const int c0 = off[node], c1 = off[node + 1];
+    const int rb = rc_base[node] - c0;
     const int4 q0 = cp[c0];
     const size_t s0 = (size_t)q0.x * B + bidx(N, q0.y, q0.z, q0.w);
-    if (flag[node] & 1) {
-        if (MODE != 2)
-            for (int c = c0; c < c1; c++) {
-                const int4 q = cp[c];
-                y[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = (T)0;
-            }
-        return;
-    }
     double dg = 0.0, of = 0.0;
     for (int c = c0; c < c1; c++) {
         const int4 q = cp[c];
-        double s[NW];
-        ifem_partial_stencil(geom[q.x], N, q.y, q.z, q.w, s);
+        const double* sw = sten + rb + c;
         const T* xm = x + (size_t)q.x * B;
         int o[NW];
         nbr_index((int)bidx(N, q.y, q.z, q.w), N + 1 - q.w, q.z, o);
-        dg += s[0];
+        dg += sw[0];
 #pragma unroll
         for (int w = 1; w < NW; w++)
-            if (inside(N, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w))) of += s[w] * (double)xm[o[w]];
+            if (inside(N, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w)))
+                of += sw[(size_t)w * n_rc] * (double)xm[o[w]];
     }
     if (MODE == 2) {
         tmp[t] = ((double)f[s0] - of) / dg;
@@ -185,10 +178,75 @@ __global__ __launch_bounds__(256) void k_iface(
     }
 }
 
-// Face path: free nodes of interior faces, each with exactly two copies.  The
-// element-wise partial stencils of both copies are stored once per level as
-// struct of arrays [copy][w][node], so consecutive lanes load consecutive
-// weights.  Same modes as k_iface; list (optional) selects positions.
+// element-wise partial stencils of listed copies, stored as [15][n]
+__global__ __launch_bounds__(128) void k_copy_stencils(const int4* __restrict__ cp, int n,
+                                                       const MacroGeom* __restrict__ geom, int N,
+                                                       double* __restrict__ sten) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int4 c = cp[t];
+    double s[NW];
+    ifem_partial_stencil(geom[c.x], N, c.y, c.z, c.w, s);
+#pragma unroll
+    for (int w = 0; w < NW; w++) sten[(size_t)w * n + t] = s[w];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_slots(T* __restrict__ y,
+                                                    const int64_t* __restrict__ slots, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[slots[t]] = (T)0;
+}
+
+// Face path: free nodes of interior faces, each with exactly two copies A
+// and B.  A face node of macro A lies on one of its faces: i = 0, j = 0,
+// k = 0 or i + j + k = N (face type 0..3).  Of the 15 directions, 7 stay in
+// the face, 4 point into the macro and 4 out of it.  The node's row is stored
+// once per level as 15 combined weights (struct of arrays [15][n2]): slots
+// 0..10 the non-outward directions of A in increasing order (in-face weights
+// summed over both sides), slots 11..14 the inward directions of B.
+struct FaceDirs {
+    int a[4][11];  // non-outward directions of a copy on face type f
+    int b[4][4];   // inward directions
+};
+constexpr int kDI[NW] = {0, -1, 1, 0, 0, 1, -1, 0, 1, 0, -1, 0, -1, 0, 1};
+constexpr int kDJ[NW] = {0, 0, 0, -1, 1, -1, 1, 0, 0, 1, 1, 0, 0, -1, -1};
+constexpr int kDK[NW] = {0, 0, 0, 0, 0, 0, 0, -1, -1, -1, -1, 1, 1, 1, 1};
+// signed distance of direction w from face type f (< 0 outward, > 0 inward)
+constexpr int face_side(int f, int w) {
+    return f == 0 ? kDI[w] : f == 1 ? kDJ[w] : f == 2 ? kDK[w] : -(kDI[w] + kDJ[w] + kDK[w]);
+}
+constexpr FaceDirs make_face_dirs() {
+    FaceDirs d{};
+    for (int f = 0; f < 4; f++) {
+        int na = 0, nb = 0;
+        for (int w = 0; w < NW; w++) {
+            if (face_side(f, w) >= 0) d.a[f][na++] = w;
+            if (face_side(f, w) > 0) d.b[f][nb++] = w;
+        }
+    }
+    return d;
+}
+inline constexpr FaceDirs kFaceDirs = make_face_dirs();
+
+__device__ __forceinline__ int face_type(int N, int i, int j, int k) {
+    return i == 0 ? 0 : j == 0 ? 1 : k == 0 ? 2 : 3;
+}
+
+template <int F, typename T>
+__device__ __forceinline__ void face_acc_a(const double* __restrict__ sw, int n2, const T* xm,
+                                           const int o[NW], double& of) {
+#pragma unroll
+    for (int e = 1; e < 11; e++) of += sw[(size_t)e * n2] * (double)xm[o[kFaceDirs.a[F][e]]];
+}
+template <int F, typename T>
+__device__ __forceinline__ void face_acc_b(const double* __restrict__ sw, int n2, const T* xm,
+                                           const int o[NW], double& of) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) of += sw[(size_t)(11 + e) * n2] * (double)xm[o[kFaceDirs.b[F][e]]];
+}
+
+// Same modes as k_iface; list (optional) selects positions.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_face2(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
@@ -197,51 +255,88 @@ __global__ __launch_bounds__(256) void k_face2(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int q = list ? list[t] : t;
-    double dg = 0.0, of = 0.0;
-    size_t slot[2];
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-        const int4 c = cp[(size_t)r * n2 + q];
-        const double* sw = sten + (size_t)r * NW * n2 + q;
-        const T* xm = x + (size_t)c.x * B;
-        int o[NW];
-        const int base = (int)bidx(N, c.y, c.z, c.w);
-        nbr_index(base, N + 1 - c.w, c.z, o);
-        slot[r] = (size_t)c.x * B + base;
-        dg += sw[0];
-#pragma unroll
-        for (int w = 1; w < NW; w++)
-            if (inside(N, c.y + dir_i(w), c.z + dir_j(w), c.w + dir_k(w)))
-                of += sw[(size_t)w * n2] * (double)xm[o[w]];
+    const int4 ca = cp[q], cb = cp[(size_t)n2 + q];
+    const int ba = (int)bidx(N, ca.y, ca.z, ca.w), bb = (int)bidx(N, cb.y, cb.z, cb.w);
+    const T* xa = x + (size_t)ca.x * B;
+    const T* xb = x + (size_t)cb.x * B;
+    const double* sw = sten + q;
+    int o[NW];
+    double of = 0.0;
+    nbr_index(ba, N + 1 - ca.w, ca.z, o);
+    switch (face_type(N, ca.y, ca.z, ca.w)) {
+        case 0: face_acc_a<0>(sw, n2, xa, o, of); break;
+        case 1: face_acc_a<1>(sw, n2, xa, o, of); break;
+        case 2: face_acc_a<2>(sw, n2, xa, o, of); break;
+        default: face_acc_a<3>(sw, n2, xa, o, of); break;
     }
+    nbr_index(bb, N + 1 - cb.w, cb.z, o);
+    switch (face_type(N, cb.y, cb.z, cb.w)) {
+        case 0: face_acc_b<0>(sw, n2, xb, o, of); break;
+        case 1: face_acc_b<1>(sw, n2, xb, o, of); break;
+        case 2: face_acc_b<2>(sw, n2, xb, o, of); break;
+        default: face_acc_b<3>(sw, n2, xb, o, of); break;
+    }
+    const double dg = sw[0];
+    const size_t sa = (size_t)ca.x * B + ba, sb = (size_t)cb.x * B + bb;
     if (MODE == 2) {
-        tmp[t] = ((double)f[slot[0]] - of) / dg;
+        tmp[t] = ((double)f[sa] - of) / dg;
         return;
     }
-    double v = dg * (double)x[slot[0]] + of;
-    if (MODE == 1) v = (double)f[slot[0]] - v;
-    y[slot[0]] = (T)v;
-    y[slot[1]] = (T)v;
+    double v = dg * (double)xa[ba] + of;
+    if (MODE == 1) v = (double)f[sa] - v;
+    y[sa] = (T)v;
+    y[sb] = (T)v;
 }
 
+// Combined face stencils: the element-wise partial stencils of both copies,
+// with each in-face direction of A matched to the direction of B that reaches
+// the same global node (through the barycentric coordinates over the shared
+// vertices).
 __global__ __launch_bounds__(128) void k_face2_stencils(const int4* __restrict__ cp, int n2,
-                                                        const MacroGeom* __restrict__ geom, int N,
+                                                        const MacroGeom* __restrict__ geom,
+                                                        const MacroTopo* __restrict__ topo, int N,
                                                         double* __restrict__ sten) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * n2) return;
-    const int r = t / n2, q = t - r * n2;
-    const int4 c = cp[t];
-    double s[NW];
-    ifem_partial_stencil(geom[c.x], N, c.y, c.z, c.w, s);
-#pragma unroll
-    for (int w = 0; w < NW; w++) sten[((size_t)r * NW + w) * n2 + q] = s[w];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n2) return;
+    const int4 ca = cp[q], cb = cp[(size_t)n2 + q];
+    double sa[NW], sb[NW];
+    ifem_partial_stencil(geom[ca.x], N, ca.y, ca.z, ca.w, sa);
+    ifem_partial_stencil(geom[cb.x], N, cb.y, cb.z, cb.w, sb);
+    const int fa = face_type(N, ca.y, ca.z, ca.w), fb = face_type(N, cb.y, cb.z, cb.w);
+    const MacroTopo& TA = topo[ca.x];
+    const MacroTopo& TB = topo[cb.x];
+    for (int e = 0; e < 11; e++) {
+        const int w = kFaceDirs.a[fa][e];
+        double v = sa[w];
+        if (face_side(fa, w) == 0) {
+            const int i = ca.y + kDI[w], j = ca.z + kDJ[w], k = ca.w + kDK[w];
+            const int mu[4] = {N - i - j - k, i, j, k};
+            int mb[4] = {0, 0, 0, 0};
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++)
+                    if (TB.vg[b] == TA.vg[a]) mb[b] = mu[a];
+            const int wb = dir_index(mb[1] - cb.y, mb[2] - cb.z, mb[3] - cb.w);
+            if (wb >= 0) v += sb[wb];
+        }
+        sten[(size_t)e * n2 + q] = v;
+    }
+    for (int e = 0; e < 4; e++) sten[(size_t)(11 + e) * n2 + q] = sb[kFaceDirs.b[fb][e]];
 }
-
+// Stored stencils of a level's interface nodes (built on first use): the
+// combined row of every face fast-path node ([15][n_f2]) and the partial
+// stencil of every copy of the other free lower-primitive nodes ([15][n_rc]).
 const double* face_stencils(Mesh& M, int lam, hipStream_t s) {
     Level& L = M.level(lam);
     if (!L.f2_sten.p && L.n_f2) {
-        L.f2_sten.alloc((size_t)2 * NW * L.n_f2);
-        k_face2_stencils<<<(2 * L.n_f2 + 127) / 128, 128, 0, s>>>(L.f2_cp.p, L.n_f2, M.d_geom.p, L.N, L.f2_sten.p);
+        L.f2_sten.alloc((size_t)NW * L.n_f2);
+        k_face2_stencils<<<(L.n_f2 + 127) / 128, 128, 0, s>>>(L.f2_cp.p, L.n_f2, M.d_geom.p,
+                                                              M.d_topo.p, L.N, L.f2_sten.p);
+        TS_HIP(hipGetLastError());
+    }
+    if (!L.rest_sten.p && L.n_rc) {
+        L.rest_sten.alloc((size_t)NW * L.n_rc);
+        k_copy_stencils<<<(L.n_rc + 127) / 128, 128, 0, s>>>(L.rc_cp.p, L.n_rc, M.d_geom.p, L.N,
+                                                             L.rest_sten.p);
         TS_HIP(hipGetLastError());
     }
     return L.f2_sten.p;
@@ -373,8 +468,9 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
                                                      L.B, tmp)
 #define TS_IF(T_, M_)                                                                         \
     k_iface<T_, M_><<<(nr + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,       \
-                                                     L.if_off.p, L.if_copy.p, L.if_flag.p, lr, \
-                                                     nr, M.d_geom.p, L.N, L.B, tmp_r)
+                                                     L.if_off.p, L.if_copy.p, L.rc_base.p,    \
+                                                     L.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
+                                                     tmp_r)
     if (n2) {
         if (dtype == TS_F64) {
             if (mode == 0) TS_F2(double, 0); else if (mode == 1) TS_F2(double, 1); else TS_F2(double, 2);
@@ -388,6 +484,13 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
         } else {
             if (mode == 0) TS_IF(float, 0); else if (mode == 1) TS_IF(float, 1); else TS_IF(float, 2);
         }
+    }
+    if (phase < 0 && L.n_dir_slots) {  // Dirichlet rows are zero
+        const unsigned g = (unsigned)((L.n_dir_slots + 255) / 256);
+        if (dtype == TS_F64)
+            k_zero_slots<double><<<g, 256, 0, s>>>((double*)y, L.dir_slots.p, L.n_dir_slots);
+        else
+            k_zero_slots<float><<<g, 256, 0, s>>>((float*)y, L.dir_slots.p, L.n_dir_slots);
     }
 #undef TS_F2
 #undef TS_IF

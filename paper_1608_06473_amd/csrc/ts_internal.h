@@ -116,9 +116,18 @@ struct Level {
     int n_f2 = 0;
     DBuf<int> f2_node;
     DBuf<int4> f2_cp;             // [2][n_f2]
-    DBuf<double> f2_sten;         // [2][15][n_f2]
-    DBuf<int> rest;               // other lower-primitive nodes (node ids)
+    DBuf<double> f2_sten;         // combined rows [15][n_f2]
+    DBuf<int> rest;               // other free lower-primitive nodes (node ids)
     int n_rest = 0;
+    // stored partial stencils of the copies of the `rest` nodes: copy c of
+    // node n has compact index rc_base[n] + (c - off[n]); [15][n_rc]
+    DBuf<int> rc_base;
+    DBuf<int4> rc_cp;
+    DBuf<double> rest_sten;
+    int n_rc = 0;
+    // block slots of every copy of every Dirichlet node (zero rows)
+    DBuf<int64_t> dir_slots;
+    int64_t n_dir_slots = 0;
     // per GS phase: positions in the face fast path / in the general lists
     DBuf<int> f2_phase[N_IF_PHASES];
     int n_f2_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};

@@ -230,20 +230,30 @@ Level& Mesh::level(int lam) {
     // face fast path: free nodes of interior faces (two copies)
     {
         std::vector<int> f2, rest;
-        std::vector<int4> c0, c1;
-        std::vector<int> f2pos(n_if, -1), restpos(n_if, -1);
+        std::vector<int4> c0, c1, rcc;
+        std::vector<int> f2pos(n_if, -1), rcb(n_if, -1);
+        std::vector<int64_t> dslots;
         for (int64_t n = 0; n < n_if; n++) {
             const bool face = n >= nv + ne * (N - 1);
-            if (face && !(flag[n] & 1) && off[n + 1] - off[n] == 2) {
+            if (flag[n] & 1) {
+                for (int c = off[n]; c < off[n + 1]; c++)
+                    dslots.push_back((int64_t)cp[c].x * L->B + bidx(N, cp[c].y, cp[c].z, cp[c].w));
+            } else if (face && off[n + 1] - off[n] == 2) {
                 f2pos[n] = (int)f2.size();
                 f2.push_back((int)n);
                 c0.push_back(cp[off[n]]);
                 c1.push_back(cp[off[n] + 1]);
             } else {
-                restpos[n] = (int)rest.size();
                 rest.push_back((int)n);
+                rcb[n] = (int)rcc.size();
+                for (int c = off[n]; c < off[n + 1]; c++) rcc.push_back(cp[c]);
             }
         }
+        L->n_rc = (int)rcc.size();
+        L->rc_base.upload(rcb);
+        L->rc_cp.upload(rcc);
+        L->n_dir_slots = (int64_t)dslots.size();
+        L->dir_slots.upload(dslots);
         std::vector<int4> c01(c0);
         c01.insert(c01.end(), c1.begin(), c1.end());
         L->n_f2 = (int)f2.size();

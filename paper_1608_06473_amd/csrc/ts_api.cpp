@@ -149,14 +149,28 @@ static double* iface_tmp(const ts_op* op, int lam) {
     return b->p;
 }
 
-// y = L x (mode 0) or y = f - L x (mode 1)
+// levels from which the lower-primitive rows run on the side stream
+constexpr int kForkLevel = 6;
+
+// y = L x (mode 0) or y = f - L x (mode 1).  The lower-primitive rows and the
+// volume rows write disjoint slots, so on large levels the former run on the
+// operator's side stream while the volume kernel runs on s.
 static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                     const void* f, hipStream_t s) {
-    launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s);
+    const bool fork = lam >= kForkLevel && op->side;
+    if (fork) {
+        TS_HIP(hipEventRecord(op->ev_fork, s));
+        TS_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, op->side);
+        TS_HIP(hipEventRecord(op->ev_join, op->side));
+    } else {
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s);
+    }
     if (uses_surrogate(op, lam))
         launch_volume(op, lam, dtype, mode, x, y, f, 0, s);
     else
         launch_ifem_volume(op, lam, dtype == TS_F16W ? TS_F32 : dtype, mode, x, y, f, 0, s);
+    if (fork) TS_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
 }
 
 static void gs_sweep(const ts_op* op, int lam, int dtype, const void* f, void* u, hipStream_t s) {
@@ -426,6 +440,9 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             op->max_level = max_level;
             op->mq = p->method == TS_IFEM ? 0 : mq_of(p->q);
             for (int lam = 2; lam <= max_level; lam++) setup_level(op, lam, S(s));
+            TS_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
+            TS_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+            TS_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
         } catch (...) {
             delete op;
             throw;

@@ -108,11 +108,11 @@ struct Level {
     DBuf<int4> lds_tiles;
     int n_lds_tiles = 0;
     int lds_kpt = 0;              // staged values per thread and plane
-    // fast path for nodes of interior faces (exactly two copies): node ids,
-    // both copies, and their partial stencils as struct of arrays
-    // [copy][w][face node] so that lane loads are coalesced; the remaining
-    // lower-primitive nodes (edges, vertices, Dirichlet faces) go through the
-    // general copy lists
+    // fast path for free nodes of interior faces (exactly two copies): node
+    // ids, both copies, and their combined rows as struct of arrays
+    // [slot][face node] so that lane loads are coalesced; the remaining free
+    // lower-primitive nodes (edges, vertices) go through the general copy
+    // lists
     int n_f2 = 0;
     DBuf<int> f2_node;
     DBuf<int4> f2_cp;             // [2][n_f2]
@@ -198,6 +198,15 @@ struct ts_op {
     int max_level = 0;
     int mq = 0;
     std::map<int, std::unique_ptr<ts::LevelOp>> lv;
+    // side stream for the lower-primitive rows, run beside the volume kernel
+    // (fork / join through events on the caller's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~ts_op() {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 namespace ts {

@@ -204,6 +204,29 @@ int ts_vcycle(ts_solver *sv, int dtype, const void *f, void *u, ts_stream s);
  * info filled when it stops early. */
 int ts_solve(ts_solver *sv, const double *f, double *u, ts_solve_info *info, ts_stream s);
 
+/* ---- asynchronous solve (request loops, continuous batching) ------------
+ * The same outer iteration as ts_solve, split so that a host loop can keep
+ * many solves in flight on their own streams and advance each when its last
+ * step has finished, without blocking:
+ *   ts_solve_begin enqueues ||f|| and the first residual on s and returns;
+ *   ts_solve_query never blocks and sets *state to TS_SOLVE_RUNNING (work in
+ *     flight), TS_SOLVE_READY (call ts_solve_step next) or TS_SOLVE_DONE
+ *     (info->status is final: TS_OK, TS_ENOCONV or TS_ENONFINITE); info
+ *     (optional) gets the history so far;
+ *   ts_solve_step enqueues one outer iteration on the stream given to
+ *     ts_solve_begin (TS_EINVAL unless the state is TS_SOLVE_READY).
+ * f and u are the caller's device vectors and must stay valid until DONE; u
+ * holds the initial guess.  Results are bitwise identical to ts_solve with
+ * the same inputs.  One host thread at a time per solver (and per mesh). */
+enum { TS_SOLVE_RUNNING = 1, TS_SOLVE_READY = 2, TS_SOLVE_DONE = 3 };
+int ts_solve_begin(ts_solver *sv, const double *f, double *u, ts_stream s);
+int ts_solve_step(ts_solver *sv);
+int ts_solve_query(ts_solver *sv, int *state, ts_solve_info *info);
+
+/* device memory currently held by all meshes, operators and solvers of the
+ * process (bytes; excludes the caller's vectors) */
+int ts_device_bytes(int64_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,10 @@ _SIGS = {
     "ts_solver_destroy": (C.c_int, [C.c_void_p]),
     "ts_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ts_solve_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ts_solve_step": (C.c_int, [C.c_void_p]),
+    "ts_solve_query": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ts_device_bytes": (C.c_int, [C.c_void_p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -262,6 +266,30 @@ def ts_solve(sv, f, u, stream=None, raise_on_fail=True):
     return rc, info
 
 
+TS_SOLVE_RUNNING, TS_SOLVE_READY, TS_SOLVE_DONE = 1, 2, 3
+
+
+def ts_solve_begin(sv, f, u, stream=None):
+    return _check(lib().ts_solve_begin(sv, _ptr(f), _ptr(u), _stream(stream)))
+
+
+def ts_solve_step(sv):
+    return _check(lib().ts_solve_step(sv))
+
+
+def ts_solve_query(sv, info=None):
+    """Non-blocking: TS_SOLVE_RUNNING / READY / DONE (info filled if given)."""
+    st = C.c_int(0)
+    _check(lib().ts_solve_query(sv, C.byref(st), C.byref(info) if info is not None else None))
+    return st.value
+
+
+def ts_device_bytes():
+    b = C.c_int64(0)
+    _check(lib().ts_device_bytes(C.byref(b)))
+    return b.value
+
+
 # ----------------------------------------------------------------- helpers
 
 def dtype_torch(dt):
@@ -303,9 +331,9 @@ class Mesh:
         ts_node_coords(self.h, level, x)
         return x.view(-1, 3)
 
-    def rhs(self, level, kind, params=()):
+    def rhs(self, level, kind, params=(), stream=None):
         f = self.zeros(level)
-        ts_rhs(self.h, level, kind, params, f)
+        ts_rhs(self.h, level, kind, params, f, stream)
         return f
 
     def norm(self, level, x, dt=TS_F64):
@@ -321,11 +349,12 @@ class Operator:
     """Owning wrapper of a ts_op handle (keeps its mesh alive)."""
 
     def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 fallback_tol=0.0):
+                 fallback_tol=0.0, stream=None):
         self.mesh = mesh
         self.method, self.q = method, q
         self.max_level = max_level
-        self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol)
+        self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol,
+                              stream)
 
     def macro_flags(self, level):
         """1 for macros whose volume rows stay IFEM on this level."""
@@ -373,11 +402,20 @@ class Solver:
         ts_vcycle(self.h, dt, f, u)
         return u
 
-    def solve(self, f, u=None, raise_on_fail=True):
+    def solve(self, f, u=None, raise_on_fail=True, stream=None):
         if u is None:
             u = self.op.mesh.zeros(self.level)
-        rc, info = ts_solve(self.h, f, u, raise_on_fail=raise_on_fail)
+        rc, info = ts_solve(self.h, f, u, stream=stream, raise_on_fail=raise_on_fail)
         return u, rc, info
+
+    def begin(self, f, u, stream=None):
+        ts_solve_begin(self.h, f, u, stream)
+
+    def step(self):
+        ts_solve_step(self.h)
+
+    def query(self, info=None):
+        return ts_solve_query(self.h, info)
 
     def __del__(self):
         if getattr(self, "h", None) is not None and _lib is not None:

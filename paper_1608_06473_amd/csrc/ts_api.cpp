@@ -130,23 +130,17 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
     op->lv[lam] = std::move(lo);
 }
 
-// Scratch buffers owned by the operator (per level): interface GS values.
-struct OpScratch {
-    std::map<int, std::unique_ptr<DBuf<double>>> tmp;
-};
-static std::map<const ts_op*, OpScratch> g_scratch;
-
+// Interface Gauss-Seidel values of one phase (sized for the largest phase),
+// owned by the operator's level.
 static double* iface_tmp(const ts_op* op, int lam) {
-    auto& sc = g_scratch[op];
-    auto& b = sc.tmp[lam];
-    if (!b) {
-        b = std::make_unique<DBuf<double>>();
+    LevelOp& lo = *op->lv.at(lam);
+    if (!lo.gs_tmp.p) {
         const Level& L = op->mesh->m.level(lam);
         int mx = 1;
         for (int p = 0; p < N_IF_PHASES; p++) mx = std::max(mx, L.n_f2_phase[p] + L.n_rest_phase[p]);
-        b->alloc(mx);
+        lo.gs_tmp.alloc(mx);
     }
-    return b->p;
+    return lo.gs_tmp.p;
 }
 
 // levels from which the lower-primitive rows run on the side stream
@@ -211,6 +205,22 @@ struct ts_solver {
     DBuf<double> r_outer;
     DBuf<float> r_in, e_in;
     DBuf<double> partial, nrm;
+    // asynchronous solve: operands, stream, pinned norms ||f||, ||r|| and the
+    // event of the last enqueued step
+    const double* af = nullptr;
+    double* au = nullptr;
+    hipStream_t as = nullptr;
+    double* hnrm = nullptr;
+    hipEvent_t ev = nullptr;
+    int state = 0;  // 0 idle, else TS_SOLVE_RUNNING / READY / DONE
+    bool have_nf = false;
+    double nf = 0.0, prev = 0.0;
+    int ups = 0;
+    ts_solve_info info{};
+    ~ts_solver() {
+        if (hnrm) (void)hipHostFree(hnrm);
+        if (ev) (void)hipEventDestroy(ev);
+    }
 };
 
 namespace ts {
@@ -320,15 +330,6 @@ static void vcycle(ts_solver* sv, int dtype, const void* f, void* u, hipStream_t
         vcycle_t<double>(sv, sv->L, dtype, (const double*)f, (double*)u, s, sv->f64, sv->u64, sv->r64);
     else
         vcycle_t<float>(sv, sv->L, dtype, (const float*)f, (float*)u, s, sv->f32, sv->u32, sv->r32);
-}
-
-static double norm2(ts_solver* sv, int dtype, const void* x, hipStream_t s) {
-    Mesh& M = sv->op->mesh->m;
-    launch_norm2_free(M, sv->L, dtype, x, sv->partial.p, sv->nrm.p, s);
-    double h = 0;
-    TS_HIP(hipMemcpyAsync(&h, sv->nrm.p, sizeof(double), hipMemcpyDeviceToHost, s));
-    TS_HIP(hipStreamSynchronize(s));
-    return h;
 }
 
 }  // namespace ts
@@ -453,7 +454,6 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
 
 int ts_op_destroy(ts_op* op) {
     return guarded([&] {
-        g_scratch.erase(op);
         delete op;
     });
 }
@@ -589,11 +589,22 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
             sv->L = level;
             sv->p = *p;
             if (sv->p.diverge_window <= 0) sv->p.diverge_window = 3;
+            // set-up work runs on a private stream, so that it does not order
+            // against other work on the device
             hipStream_t s = nullptr;
-            coarse_setup(sv, s);
+            TS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            try {
+                coarse_setup(sv, s);
+            } catch (...) {
+                (void)hipStreamDestroy(s);
+                throw;
+            }
+            TS_HIP(hipStreamDestroy(s));
             Mesh& M = op->mesh->m;
             sv->partial.alloc(norm_partial_count(M, level));
-            sv->nrm.alloc(1);
+            sv->nrm.alloc(2);
+            TS_HIP(hipHostMalloc((void**)&sv->hnrm, 2 * sizeof(double), hipHostMallocDefault));
+            TS_HIP(hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming));
         } catch (...) {
             delete sv;
             throw;
@@ -614,72 +625,155 @@ int ts_vcycle(ts_solver* sv, int dtype, const void* f, void* u, ts_stream s) {
     });
 }
 
+}  // extern "C"
+
+namespace ts {
+
+// residual r = f - L u on the finest level in FP64 and its norm into nrm[1]
+static void outer_residual(ts_solver* sv, hipStream_t st) {
+    Mesh& M = sv->op->mesh->m;
+    op_rows(sv->op, sv->L, TS_F64, 1, sv->au, sv->r_outer.p, sv->af, st);
+    launch_norm2_free(M, sv->L, TS_F64, sv->r_outer.p, sv->partial.p, sv->nrm.p + 1, st);
+}
+
+static void solve_begin(ts_solver* sv, const double* f, double* u, hipStream_t st) {
+    Mesh& M = sv->op->mesh->m;
+    const Level& L = M.level(sv->L);
+    TS_REQUIRE(sv->state == 0 || sv->state == TS_SOLVE_DONE, TS_EINVAL,
+               "a solve is already in progress on this solver");
+    if (!sv->r_outer.p) sv->r_outer.alloc(L.len);
+    if (sv->p.precision != TS_F64 && !sv->r_in.p) {
+        sv->r_in.alloc(L.len);
+        sv->e_in.alloc(L.len);
+    }
+    sv->af = f;
+    sv->au = u;
+    sv->as = st;
+    sv->have_nf = false;
+    sv->ups = 0;
+    memset(&sv->info, 0, sizeof(sv->info));
+    launch_norm2_free(M, sv->L, TS_F64, f, sv->partial.p, sv->nrm.p, st);
+    outer_residual(sv, st);
+    TS_HIP(hipMemcpyAsync(sv->hnrm, sv->nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TS_HIP(hipEventRecord(sv->ev, st));
+    sv->state = TS_SOLVE_RUNNING;
+}
+
+// one outer iteration: FP64 V-cycle on u, or a V-cycle on the rounded
+// residual in FP32 / FP16-weight arithmetic added to u; then the new residual
+static void solve_step(ts_solver* sv) {
+    TS_REQUIRE(sv->state == TS_SOLVE_READY, TS_EINVAL, "the solver is not ready for a step");
+    Mesh& M = sv->op->mesh->m;
+    const Level& L = M.level(sv->L);
+    hipStream_t st = sv->as;
+    const int prec = sv->p.precision;
+    if (prec == TS_F64) {
+        vcycle(sv, TS_F64, sv->af, sv->au, st);
+    } else {
+        launch_cast(sv->r_outer.p, TS_F64, sv->r_in.p, TS_F32, L.len, st);
+        launch_fill(sv->e_in.p, TS_F32, L.len, 0.0, st);
+        vcycle(sv, prec, sv->r_in.p, sv->e_in.p, st);
+        launch_axpy(1.0, sv->e_in.p, TS_F32, sv->au, L.len, st);
+    }
+    sv->info.cycles++;
+    outer_residual(sv, st);
+    TS_HIP(hipMemcpyAsync(sv->hnrm + 1, sv->nrm.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    TS_HIP(hipEventRecord(sv->ev, st));
+    sv->state = TS_SOLVE_RUNNING;
+}
+
+// after the last enqueued step finished: read its norms and decide
+static void solve_advance(ts_solver* sv) {
+    ts_solve_info& I = sv->info;
+    auto finish = [&](int status) {
+        I.status = status;
+        sv->state = TS_SOLVE_DONE;
+    };
+    if (!sv->have_nf) {
+        sv->have_nf = true;
+        sv->nf = sv->hnrm[0];
+        if (!std::isfinite(sv->nf)) return finish(TS_ENONFINITE);
+        if (sv->nf == 0.0) {  // f = 0: the solution is 0
+            const Level& L = sv->op->mesh->m.level(sv->L);
+            launch_fill(sv->au, TS_F64, L.len, 0.0, sv->as);
+            TS_HIP(hipEventRecord(sv->ev, sv->as));
+            I.rel_residual = 0.0;
+            return finish(TS_OK);
+        }
+    }
+    const double rel = sv->hnrm[1] / sv->nf;
+    I.rel_residual = rel;
+    if (I.n_hist < TS_MAX_HIST) I.hist[I.n_hist++] = rel;
+    if (!std::isfinite(rel)) return finish(TS_ENONFINITE);
+    if (rel <= sv->p.rtol) return finish(TS_OK);
+    if (I.cycles > 0) {
+        sv->ups = rel > sv->prev ? sv->ups + 1 : 0;
+        if (sv->ups >= sv->p.diverge_window) return finish(TS_ENOCONV);
+    }
+    sv->prev = rel;
+    if (I.cycles >= sv->p.max_cycles) return finish(TS_ENOCONV);
+    sv->state = TS_SOLVE_READY;
+}
+
+static int solve_query(ts_solver* sv) {
+    if (sv->state == TS_SOLVE_RUNNING) {
+        const hipError_t e = hipEventQuery(sv->ev);
+        if (e == hipErrorNotReady) return TS_SOLVE_RUNNING;
+        TS_HIP(e);
+        solve_advance(sv);
+    }
+    return sv->state;
+}
+
+}  // namespace ts
+
+extern "C" {
+
+int ts_device_bytes(int64_t* bytes) {
+    return guarded([&] {
+        TS_REQUIRE(bytes, TS_EINVAL, "null argument");
+        *bytes = g_dev_bytes.load();
+    });
+}
+
+int ts_solve_begin(ts_solver* sv, const double* f, double* u, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(sv && f && u && (const void*)f != (const void*)u, TS_EINVAL, "bad arguments");
+        solve_begin(sv, f, u, S(s));
+    });
+}
+
+int ts_solve_step(ts_solver* sv) {
+    return guarded([&] {
+        TS_REQUIRE(sv, TS_EINVAL, "null solver");
+        solve_step(sv);
+    });
+}
+
+int ts_solve_query(ts_solver* sv, int* state, ts_solve_info* info) {
+    return guarded([&] {
+        TS_REQUIRE(sv && state, TS_EINVAL, "null argument");
+        TS_REQUIRE(sv->state != 0, TS_EINVAL, "no solve was started on this solver");
+        *state = solve_query(sv);
+        if (info) *info = sv->info;
+    });
+}
+
 int ts_solve(ts_solver* sv, const double* f, double* u, ts_solve_info* info, ts_stream s) {
     return guarded([&] {
         TS_REQUIRE(sv && f && u && info, TS_EINVAL, "null argument");
-        hipStream_t st = S(s);
-        Mesh& M = sv->op->mesh->m;
-        const Level& L = M.level(sv->L);
-        memset(info, 0, sizeof(*info));
-        const double nf = norm2(sv, TS_F64, f, st);
-        TS_REQUIRE(std::isfinite(nf), TS_ENONFINITE, "right-hand side is not finite");
-        if (nf == 0.0) {
-            launch_fill(u, TS_F64, L.len, 0.0, st);
-            TS_HIP(hipStreamSynchronize(st));
-            info->status = TS_OK;
-            return;
+        solve_begin(sv, f, u, S(s));
+        for (;;) {
+            TS_HIP(hipEventSynchronize(sv->ev));
+            const int st = solve_query(sv);
+            if (st == TS_SOLVE_DONE) break;
+            solve_step(sv);
         }
-        const int prec = sv->p.precision;
-        if (prec != TS_F64 && !sv->r_outer.p) {
-            sv->r_outer.alloc(L.len);
-            sv->r_in.alloc(L.len);
-            sv->e_in.alloc(L.len);
-        }
-        double* r = sv->r_outer.p;
-        if (prec == TS_F64 && !r) {
-            sv->r_outer.alloc(L.len);
-            r = sv->r_outer.p;
-        }
-        op_rows(sv->op, sv->L, TS_F64, 1, u, r, f, st);
-        double rel = norm2(sv, TS_F64, r, st) / nf;
-        info->hist[info->n_hist++] = rel;
-        int ups = 0;
-        double prev = rel;
-        int status = TS_OK;
-        int c = 0;
-        while (rel > sv->p.rtol) {
-            if (c >= sv->p.max_cycles) {
-                status = TS_ENOCONV;
-                break;
-            }
-            if (prec == TS_F64) {
-                vcycle(sv, TS_F64, f, u, st);
-            } else {
-                launch_cast(r, TS_F64, sv->r_in.p, TS_F32, L.len, st);
-                launch_fill(sv->e_in.p, TS_F32, L.len, 0.0, st);
-                vcycle(sv, prec, sv->r_in.p, sv->e_in.p, st);
-                launch_axpy(1.0, sv->e_in.p, TS_F32, u, L.len, st);
-            }
-            c++;
-            op_rows(sv->op, sv->L, TS_F64, 1, u, r, f, st);
-            rel = norm2(sv, TS_F64, r, st) / nf;
-            if (info->n_hist < TS_MAX_HIST) info->hist[info->n_hist++] = rel;
-            if (!std::isfinite(rel)) {
-                status = TS_ENONFINITE;
-                break;
-            }
-            ups = rel > prev ? ups + 1 : 0;
-            prev = rel;
-            if (ups >= sv->p.diverge_window) {
-                status = TS_ENOCONV;
-                break;
-            }
-        }
-        info->cycles = c;
-        info->rel_residual = rel;
-        info->status = status;
+        TS_HIP(hipEventSynchronize(sv->ev));
+        *info = sv->info;
+        const int status = sv->info.status;
         if (status != TS_OK)
-            throw Error{status, status == TS_ENONFINITE ? "iterate became non-finite"
+            throw Error{status, status == TS_ENONFINITE ? "right-hand side or iterate is not finite"
                                                         : "no convergence to the tolerance"};
     });
 }

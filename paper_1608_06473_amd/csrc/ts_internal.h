@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <array>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <string>
@@ -34,6 +35,9 @@ struct Error {
     } while (0)
 
 // ------------------------------------------------------------ device buffer
+// device bytes held by all library objects of the process
+inline std::atomic<int64_t> g_dev_bytes{0};
+
 template <typename X>
 struct DBuf {
     X* p = nullptr;
@@ -43,7 +47,10 @@ struct DBuf {
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            g_dev_bytes -= (int64_t)(n * sizeof(X));
+        }
         p = nullptr;
         n = 0;
     }
@@ -56,6 +63,7 @@ struct DBuf {
             throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(X)) + " bytes failed"};
         }
         n = count;
+        g_dev_bytes += (int64_t)(count * sizeof(X));
     }
     void upload(const std::vector<X>& h) {
         alloc(h.size());
@@ -184,6 +192,7 @@ struct LevelOp {
     DBuf<int> sur_list, ifem_list;
     int n_sur = 0, n_ifem = 0;
     bool has_coef = false;
+    DBuf<double> gs_tmp;   // interface Gauss-Seidel values of one phase
 };
 
 }  // namespace ts

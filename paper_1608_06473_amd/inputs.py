@@ -177,3 +177,17 @@ def gaussian_bumps(seed, r_in, r_out=1.0, n_bumps=8):
         out[b, 3] = rng.uniform(0.05, 0.15)
         out[b, 4] = rng.uniform(-1.0, 1.0)
     return out.reshape(-1)
+
+
+def serving_trace(n, rate=50.0, seed=0, levels=(4, 5, 6, 7), r_in=(0.4, 0.7)):
+    """Request trace of shell solves: Poisson arrivals (exponential gaps with
+    mean 1/rate, PCG64 seed `seed`), level uniform on `levels` and inner radius
+    ~ U[r_in] (PCG64 seed `seed` + 1).  The right-hand side of request i is
+    gaussian_bumps(i, r_inner) on the shell r_inner < r < 1."""
+    ra = np.random.default_rng(seed)
+    rb = np.random.default_rng(seed + 1)
+    t = np.cumsum(ra.exponential(1.0 / rate, size=int(n)))
+    lv = rb.choice(np.asarray(levels), size=int(n))
+    ri = rb.uniform(r_in[0], r_in[1], size=int(n))
+    return [{"id": i, "t": float(t[i]), "level": int(lv[i]), "r_in": float(ri[i])}
+            for i in range(int(n))]

@@ -1,0 +1,243 @@
+"""Continuous-batching request loop for shell Poisson solves on one GPU.
+
+Requests arrive at their trace times: a level, an inner radius, and a
+right-hand side of Gaussian bumps.  A request is admitted when it fits the
+HBM budget and a slot is free.  A worker thread then builds its mesh,
+surrogate operator and multigrid solver on the request's own stream, and
+enqueues the start of the solve (ts_solve_begin).  The scheduler thread polls
+every active solve without blocking (ts_solve_query) and, level by level,
+enqueues the next refinement iteration (ts_solve_step) of each request whose
+last one has finished.  Work of many requests is therefore in flight on the
+device at once, and requests arriving meanwhile join as slots and memory free
+up.  A request retires when its FP64 relative residual reaches the tolerance.
+
+Every request runs the same sequence of kernels on its own data whatever else
+is in flight (no atomics, fixed reduction order), so a result is bitwise the
+same alone and in the mix.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import time
+
+import numpy as np
+
+from . import (TS_F32, TS_F64, TS_LSQP, TS_OK, TS_RHS_BUMPS, TS_SOLVE_DONE, TS_SOLVE_READY,
+               Mesh, Operator, Solver, inputs, ts_device_bytes, ts_solve_info)
+
+TOPOLOGIES = {
+    # the 288-macro shell (faces split 2 x 2, two radial layers) scaled to the
+    # request's inner radius; the middle layer sits halfway
+    "shell288": lambda r_in: inputs.shell288(r_in, 1.0),
+    "shell36": lambda r_in: inputs.shell36(r_in, 1.0),
+}
+N_MACROS = {"shell288": 288, "shell36": 36}
+
+
+def request_bytes(n_macros, level, precision=TS_F32):
+    """Admission estimate of the device bytes of one request: caller vectors
+    f, u (FP64), the outer residual, the FP32 correction pair and three
+    V-cycle vectors per level (FP32 or FP64), the stored interface stencils,
+    plus a fixed allowance for coefficients, lists and the coarse inverse."""
+    def vec(lam):
+        N = 2 ** lam
+        return n_macros * (N + 1) * (N + 2) * (N + 3) // 6
+    per_level = 12 if precision != TS_F64 else 24
+    b = vec(level) * (16 + 8 + (8 if precision != TS_F64 else 0) + 8)
+    for lam in range(2, level + 1):
+        b += vec(lam) * per_level
+    return int(b + 32 * 2 ** 20)
+
+
+class Request:
+    __slots__ = ("id", "t", "level", "r_in", "bytes", "t_admit", "t_ready", "t_done", "stream",
+                 "mesh", "op", "sv", "f", "u", "info", "status", "cycles", "rel", "u_host",
+                 "error")
+
+    def __init__(self, rec, n_macros, precision):
+        self.id, self.t, self.level, self.r_in = rec["id"], rec["t"], rec["level"], rec["r_in"]
+        self.bytes = request_bytes(n_macros, self.level, precision)
+        self.t_admit = self.t_ready = self.t_done = None
+        self.stream = self.mesh = self.op = self.sv = self.f = self.u = None
+        self.info = ts_solve_info()
+        self.status = None
+        self.cycles = 0
+        self.rel = None
+        self.u_host = None
+        self.error = None
+
+
+class Server:
+    """One GPU, many requests in flight.
+
+    topology: key of TOPOLOGIES; q, fallback_tol: surrogate degree and the
+    per-macro IFEM fallback tolerance; precision: TS_F32 (FP32 V-cycles with
+    FP64 refinement), TS_F16W or TS_F64; rtol: FP64 relative residual to
+    reach; hbm_budget: bytes the admitted requests may use (estimate);
+    max_active: slots; keep: ids whose solutions are copied to the host.
+    """
+
+    def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
+                 hbm_budget=64 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
+                 keep=(), gc_batch=8):
+        import torch
+        self.torch = torch
+        self.topology = topology
+        self.n_macros = N_MACROS[topology]
+        self.q, self.precision, self.rtol = q, precision, rtol
+        self.max_cycles = max_cycles
+        self.hbm_budget = hbm_budget
+        self.max_active = max_active
+        self.fallback_tol = fallback_tol
+        self.keep = set(keep)
+        self.gc_batch = gc_batch
+        self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
+
+    # -- per request ---------------------------------------------------------
+    def _setup(self, r):
+        torch = self.torch
+        r.stream = torch.cuda.Stream()
+        vtx, tet = TOPOLOGIES[self.topology](r.r_in)
+        r.mesh = Mesh(vtx, tet)
+        r.op = Operator(r.mesh, r.level, method=TS_LSQP, q=self.q, sample_j=2,
+                        fallback_tol=self.fallback_tol, stream=r.stream)
+        r.sv = Solver(r.op, r.level, precision=self.precision, rtol=self.rtol,
+                      max_cycles=self.max_cycles)
+        params = inputs.gaussian_bumps(r.id, r.r_in, 1.0)
+        with torch.cuda.stream(r.stream):
+            r.f = r.mesh.rhs(r.level, TS_RHS_BUMPS, params, stream=r.stream)
+            r.u = r.mesh.zeros(r.level)
+        r.sv.begin(r.f, r.u, r.stream)
+        return r
+
+    def _retire(self, r, now):
+        r.t_done = now
+        r.status = r.info.status
+        r.cycles = r.info.cycles
+        r.rel = r.info.rel_residual
+        if r.id in self.keep:
+            with self.torch.cuda.stream(r.stream):
+                r.u_host = r.u.cpu().numpy()
+
+    @staticmethod
+    def _destroy(reqs):
+        for r in reqs:
+            r.sv = r.op = r.mesh = r.f = r.u = None
+            r.stream = None
+
+    # -- loop ----------------------------------------------------------------
+    def run(self, trace):
+        """Serve the trace (list of dicts id, t, level, r_in) in wall-clock
+        time and return (requests, summary)."""
+        torch = self.torch
+        reqs = [Request(rec, self.n_macros, self.precision) for rec in trace]
+        pending = collections.deque(sorted(reqs, key=lambda r: r.t))
+        waiting = collections.deque()
+        setting_up = {}
+        active = collections.defaultdict(list)
+        grave = []
+        used = 0
+        peak_used = 0
+        peak_dev = 0
+        occ_area = 0.0
+        n_active = 0
+        t0 = time.perf_counter()
+        t_last = 0.0
+        while pending or waiting or setting_up or any(active.values()):
+            now = time.perf_counter() - t0
+            occ_area += n_active * (now - t_last)
+            t_last = now
+            while pending and pending[0].t <= now:
+                waiting.append(pending.popleft())
+            # admission in arrival order, by slot and memory
+            while waiting and n_active + len(setting_up) < self.max_active:
+                r = waiting[0]
+                if used + r.bytes > self.hbm_budget:
+                    if grave:
+                        used -= sum(g.bytes for g in grave)
+                        self._destroy(grave)
+                        grave = []
+                        continue
+                    if n_active + len(setting_up) == 0:
+                        raise RuntimeError("request %d needs %d bytes, over the HBM budget"
+                                           % (r.id, r.bytes))
+                    break
+                waiting.popleft()
+                used += r.bytes
+                peak_used = max(peak_used, used)
+                r.t_admit = now
+                setting_up[self.pool.submit(self._setup, r)] = r
+            # requests whose set-up finished join the active set
+            for fut in [f for f in setting_up if f.done()]:
+                r = setting_up.pop(fut)
+                fut.result()
+                r.t_ready = time.perf_counter() - t0
+                active[r.level].append(r)
+                n_active += 1
+            progressed = False
+            # one refinement iteration for every ready request, level by level
+            for lvl in sorted(active):
+                still = []
+                for r in active[lvl]:
+                    st = r.sv.query(r.info)
+                    if st == TS_SOLVE_READY:
+                        r.sv.step()
+                        progressed = True
+                        still.append(r)
+                    elif st == TS_SOLVE_DONE:
+                        self._retire(r, time.perf_counter() - t0)
+                        grave.append(r)
+                        n_active -= 1
+                        progressed = True
+                    else:
+                        still.append(r)
+                active[lvl] = still
+            if len(grave) >= self.gc_batch:
+                peak_dev = max(peak_dev, ts_device_bytes())
+                used -= sum(g.bytes for g in grave)
+                self._destroy(grave)
+                grave = []
+            if not progressed:
+                time.sleep(50e-6)
+        peak_dev = max(peak_dev, ts_device_bytes())
+        self._destroy(grave)
+        torch.cuda.synchronize()
+        t_end = time.perf_counter() - t0
+        return reqs, summarize(reqs, t_end, occ_area, peak_used, peak_dev)
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
+def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
+    done = [r for r in reqs if r.t_done is not None]
+    ok = [r for r in done if r.status == TS_OK]
+    lat = np.array([r.t_done - r.t for r in done]) if done else np.zeros(1)
+    first = min(r.t for r in reqs)
+    last = max(r.t_done for r in done) if done else first
+    by_level = {}
+    for lvl in sorted({r.level for r in done}):
+        la = np.array([r.t_done - r.t for r in done if r.level == lvl])
+        by_level[int(lvl)] = {"n": int(la.size),
+                              "p50_ms": round(float(np.percentile(la, 50)) * 1e3, 2),
+                              "p99_ms": round(float(np.percentile(la, 99)) * 1e3, 2),
+                              "cycles_mean": round(float(np.mean([r.cycles for r in done
+                                                                  if r.level == lvl])), 2)}
+    return {
+        "requests": len(reqs),
+        "completed_ok": len(ok),
+        "failed": len(done) - len(ok),
+        "offered_rate_per_s": round(len(reqs) / max(max(r.t for r in reqs) - first, 1e-9), 2),
+        "solves_per_s": round(len(ok) / max(last - first, 1e-9), 3),
+        "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "mean_setup_ms": round(float(np.mean([r.t_ready - r.t_admit for r in done])) * 1e3, 2),
+        "mean_queue_ms": round(float(np.mean([r.t_admit - r.t for r in done])) * 1e3, 2),
+        "mean_active": round(occ_area / max(t_end, 1e-9), 2),
+        "peak_admitted_gb": round(peak_used / 2 ** 30, 3),
+        "peak_library_gb": round(peak_dev / 2 ** 30, 3),
+        "max_rel_residual": float(max(r.rel for r in ok)) if ok else None,
+        "wall_s": round(t_end, 3),
+        "by_level": by_level,
+    }

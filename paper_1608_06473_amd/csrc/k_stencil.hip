@@ -88,16 +88,23 @@ __device__ __forceinline__ void volume_body(const T* xm, T* ym, const T* fm, WP&
 template <typename T, int MODE, int R>
 __global__ __launch_bounds__(VOL_THREADS) void k_ifem_volume(
     const T* x, T* y, const T* __restrict__ f, const MacroGeom* __restrict__ geom,
-    const int2* __restrict__ tiles, int n_tiles, int nt, const int* __restrict__ mlist, int N,
-    int64_t B, int colour) {
+    const int2* __restrict__ tiles, int n_tiles, int nt, const int* __restrict__ mlist,
+    const unsigned* __restrict__ gs_lanes, int N, int64_t B, int colour) {
     int macro, tile;
     if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
     const int2 td = tiles[tile];
     const int k0 = td.x, Mr = N - 1 - k0;
-    const int pos = td.y + (int)threadIdx.x;
-    if (pos >= (Mr - 1) * Mr / 2) return;
     int i, j;
-    pos_to_ij(pos, Mr, i, j);
+    if (MODE == 2) {  // colour-class lane order
+        const unsigned e = gs_lanes[(size_t)tile * VOL_THREADS + threadIdx.x];
+        if (e == 0xFFFFFFFFu) return;
+        i = (int)(e & 0xFFFFu);
+        j = (int)(e >> 16);
+    } else {
+        const int pos = td.y + (int)threadIdx.x;
+        if (pos >= (Mr - 1) * Mr / 2) return;
+        pos_to_ij(pos, Mr, i, j);
+    }
     const int kend = min(N - 1 - i - j, k0 + R - 1);
     IfemW wp;
     wp.g = geom[macro];
@@ -429,11 +436,11 @@ static void run_ifem_volume(const Mesh& M, const Level& L, int mode, const void*
     T* yp = (T*)y;
     const T* fp = (const T*)f;
     if (mode == 0)
-        k_ifem_volume<T, 0, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
+        k_ifem_volume<T, 0, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
     else if (mode == 1)
-        k_ifem_volume<T, 1, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
+        k_ifem_volume<T, 1, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
     else
-        k_ifem_volume<T, 2, VOL_R><<<grid, blk, 0, s>>>(yp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.N, L.B, colour);
+        k_ifem_volume<T, 2, VOL_R><<<grid, blk, 0, s>>>(yp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
 }
 
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,

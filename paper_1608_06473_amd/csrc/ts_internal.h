@@ -108,6 +108,7 @@ struct Level {
     // volume tiles: (k0, first position in plane k0's interior triangle)
     DBuf<int2> tiles;
     int n_tiles = 0;
+    DBuf<unsigned> gs_lanes_ifem;  // per tile and lane: i | j << 16 (GS order)
     // all-slot tiles: (plane k, first slot of a chunk of plane k)
     DBuf<int2> slot_tiles;
     int n_slot_tiles = 0;
@@ -116,6 +117,7 @@ struct Level {
     DBuf<int4> lds_tiles;
     int n_lds_tiles = 0;
     int lds_kpt = 0;              // staged values per thread and plane
+    DBuf<unsigned> gs_lanes;      // per tile and lane: i | j << 16 (GS order)
     // fast path for free nodes of interior faces (exactly two copies): node
     // ids, both copies, and their combined rows as struct of arrays
     // [slot][face node] so that lane loads are coalesced; the remaining free

@@ -258,7 +258,8 @@ template <class WP, typename T, typename W, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS)
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
-                int nt, const int* __restrict__ mlist, int N, int64_t B, int colour) {
+                int nt, const int* __restrict__ mlist, const unsigned* __restrict__ gs_lanes,
+                int N, int64_t B, int colour) {
     constexpr int PF = TS_VOL_PF;
     int macro, tile;
     if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
@@ -270,7 +271,15 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     // stays inside the staged range, so reads need no guard
     int i = 1, j = j0;
     bool act;
-    if (i0 > 0) {
+    if (MODE == 2) {
+        // colour-class order of the tile's columns
+        const unsigned e = gs_lanes[(size_t)tile * VOL_THREADS + tid];
+        act = e != 0xFFFFFFFFu;
+        if (act) {
+            i = (int)(e & 0xFFFFu);
+            j = (int)(e >> 16);
+        }
+    } else if (i0 > 0) {
         i = i0 + tid;
         act = i <= Mr - j0;
         if (!act) i = 1;
@@ -321,6 +330,30 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     const W invN = (W)1 / (W)N;
     W z = (W)k0 * invN - (W)0.25;
     int col = (i + 2 * j + 3 * k0) & 3;
+    // Right-hand side, loaded ahead of use: a Gauss-Seidel lane needs f only
+    // on the steps of the colour being updated (every fourth), all issued
+    // here; the residual streams f through a ring PF steps ahead.
+    constexpr int NG = (R + 3) / 4;
+    T fg[MODE == 2 ? NG : 1];
+    T fr[MODE == 1 ? PF : 1];
+    int idf = idx;
+    if constexpr (MODE == 2) {
+        const int r0 = (3 * (colour - col)) & 3;  // col + 3 r = colour (mod 4)
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if ((r & 3) == r0) fg[r >> 2] = r < nlive ? fm[idf] : (T)0;
+            const int Af = N + 1 - (k0 + r);
+            idf += Af * (Af + 1) / 2 - j;
+        }
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int d = 0; d < PF; d++) {
+            fr[d] = d < nlive ? fm[idf] : (T)0;
+            const int Af = N + 1 - (k0 + d);
+            idf += Af * (Af + 1) / 2 - j;
+        }
+    }
     T pm[7], p0[7], pp[7];
 #pragma unroll
     for (int st = 0; st < R + 2; st++) {
@@ -352,16 +385,32 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
         }
         if (st >= 2) {
             const int r = st - 2;  // step k = k0 + r
-            W sw[NW];
-            wp.weights_z(z, sw);
-            const T off = off_sum<T, W>(sw, pm, p0, pp);
             const bool live = r < nlive;
             if (MODE == 2) {
-                if (live && col == colour) ym[idx] = (fm[idx] - off) / (T)sw[0];
+                // only the lanes of the colour being updated evaluate weights;
+                // with the colour-class lane order whole wavefronts skip
+                if (live && col == colour) {
+                    W sw[NW];
+                    wp.weights_z(z, sw);
+                    const T off = off_sum<T, W>(sw, pm, p0, pp);
+                    ym[idx] = (fg[r >> 2] - off) / (T)sw[0];
+                }
                 col = (col + 3) & 3;
             } else {
+                W sw[NW];
+                wp.weights_z(z, sw);
+                const T off = off_sum<T, W>(sw, pm, p0, pp);
                 const T v = (T)sw[0] * p0[0] + off;
-                if (live) ym[idx] = MODE == 0 ? v : fm[idx] - v;
+                if (MODE == 0) {
+                    if (live) ym[idx] = v;
+                } else {
+                    if (live) ym[idx] = fr[r % PF] - v;
+                    if (r + PF < R) {
+                        fr[r % PF] = r + PF < nlive ? fm[idf] : (T)0;
+                        const int Af = N + 1 - (k0 + r + PF);
+                        idf += Af * (Af + 1) / 2 - j;
+                    }
+                }
             }
             const int Ak = N + 1 - (k0 + r);  // side of plane k
             idx += Ak * (Ak + 1) / 2 - j;

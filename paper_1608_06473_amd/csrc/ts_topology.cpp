@@ -284,6 +284,28 @@ Level& Mesh::level(int lam) {
     }
     L->tiles.upload(tiles);
     L->n_tiles = (int)tiles.size();
+    // Gauss-Seidel lane order of these tiles: positions sorted (stably) by
+    // (i + 2j) mod 4 (one colour class per wavefront and plane)
+    {
+        std::vector<unsigned> lm((size_t)tiles.size() * VOL_THREADS, 0xFFFFFFFFu);
+        for (size_t t = 0; t < tiles.size(); t++) {
+            const int k0 = tiles[t].x, Mr = N - 1 - k0;
+            const int npos = (Mr - 1) * Mr / 2;
+            std::vector<std::pair<int, int>> pos;
+            int p = 0;
+            for (int j = 1; j <= Mr - 1; j++)
+                for (int i = 1; i <= Mr - j; i++, p++)
+                    if (p >= tiles[t].y && p < std::min(npos, tiles[t].y + VOL_THREADS))
+                        pos.push_back({i, j});
+            std::stable_sort(pos.begin(), pos.end(), [](const std::pair<int, int>& a,
+                                                        const std::pair<int, int>& b) {
+                return ((a.first + 2 * a.second) & 3) < ((b.first + 2 * b.second) & 3);
+            });
+            for (size_t l = 0; l < pos.size(); l++)
+                lm[t * VOL_THREADS + l] = (unsigned)pos[l].first | ((unsigned)pos[l].second << 16);
+        }
+        L->gs_lanes_ifem.upload(lm);
+    }
     // LDS-staged tiles: whole rows of plane k0's interior up to 256
     // positions, long rows split; the staged range of plane p covers rows
     // j0-1 .. j1 of that plane
@@ -320,6 +342,31 @@ Level& Mesh::level(int lam) {
     L->lds_tiles.upload(lt);
     L->n_lds_tiles = (int)lt.size();
     L->lds_kpt = (int)((maxcnt + VOL_THREADS - 1) / VOL_THREADS);
+    // Gauss-Seidel lane order: the columns of every tile sorted (stably) by
+    // (i + 2j) mod 4, so that a wavefront holds one colour class per plane
+    // and skips the planes where its class is not being updated
+    {
+        std::vector<unsigned> lm((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
+        for (size_t t = 0; t < lt.size(); t++) {
+            const int4 d = lt[t];
+            const int Mr = N - 1 - d.x;
+            std::vector<std::pair<int, int>> pos;
+            if (d.w > 0) {
+                for (int i = d.w; i <= std::min(d.w + VOL_THREADS - 1, Mr - d.y); i++)
+                    pos.push_back({i, d.y});
+            } else {
+                for (int j = d.y; j < d.z; j++)
+                    for (int i = 1; i <= Mr - j; i++) pos.push_back({i, j});
+            }
+            std::stable_sort(pos.begin(), pos.end(), [](const std::pair<int, int>& a,
+                                                        const std::pair<int, int>& b) {
+                return ((a.first + 2 * a.second) & 3) < ((b.first + 2 * b.second) & 3);
+            });
+            for (size_t l = 0; l < pos.size(); l++)
+                lm[t * VOL_THREADS + l] = (unsigned)pos[l].first | ((unsigned)pos[l].second << 16);
+        }
+        L->gs_lanes.upload(lm);
+    }
     // all-slot tiles: every plane k = 0..N in chunks of 256 slots
     std::vector<int2> st;
     for (int k = 0; k <= N; k++) {

@@ -8,12 +8,16 @@ and resident in HBM before timing starts.
 
 Printed JSON line (one): metric / value (GDoF/s of the whole operator), the
 roofline of the dominant kernel (surrogate volume kernel, HBM-bound: 16
-algorithmic bytes per interior node, x read once and y written once), the
-IFEM apply on the same GPU, the q = 4 surrogate, a Gauss-Seidel sweep, and
-the CPU oracle timed on a bounded sample of the same rows.
+algorithmic bytes per interior node, x read once and y written once; traffic
+from the committed rocprofv3 counter record of the same kernel source), the
+IFEM apply on the same GPU, q = 4, FP32 and FP16-weight applies, the residual,
+Gauss-Seidel sweeps, V(3,3) solves to 1e-10 in FP64 and with FP32 / FP16-weight
+cycles under FP64 refinement, a bounded run of the serve loop, and the CPU
+oracle timed on the free rows of the same operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--level 7] [--mesh shell288] [--only-volume]
+       [--level 7] [--mesh shell288] [--only-volume] [--no-solve] [--no-serve]
+       [--serve-requests 30]
 """
 from __future__ import annotations
 
@@ -46,34 +50,109 @@ def time_events(fn, reps, stream):
     return start.elapsed_time(stop) / reps
 
 
-def cpu_baseline(vtx, tet, lam, q, coeffs, x_canon, n_free_total, budget_s=12.0):
-    """The oracle's surrogate operator on a random sample of the workload's
-    rows (all unique free nodes equally likely), scaled to GDoF/s."""
+KERNEL_SOURCES = ["paper_1608_06473_amd/csrc/ts_surrogate.h",
+                  "paper_1608_06473_amd/csrc/k_surr_inst.hip"]
+PMC_RECORD = "profiles/pmc_k_surr_lds_q2_shell288_l7.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the volume kernel from the committed counter
+    summary (its `record:` line: FETCH_SIZE and WRITE_SIZE in KiB per
+    dispatch, scaled by the factors measured on a plain device copy), or None
+    when the summary is missing or was taken on another version of the kernel
+    source."""
+    path = os.path.join(ROOT, PMC_RECORD)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("record: "):
+                rec = json.loads(ln[len("record: "):])
+    if rec is None:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return int((rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+               * 1024)
+
+
+def cpu_baseline(vtx, tet, lam, q, x_canon, n_free_total, min_s=10.0):
+    """The oracle's surrogate operator (its own fit) on all free rows of the
+    workload (repeated passes until about min_s seconds of CPU work), in
+    GDoF/s."""
     import numpy as np
 
     import oracle
     O = oracle.Mesh(vtx, tet)
     N = 2 ** lam
-    mask = O.dirichlet_mask(N)
-    free = np.flatnonzero(~mask)
-    rng = np.random.default_rng(123)
+    coeffs = O.fit(N, oracle.LSQP, q, 2)
+    free = np.flatnonzero(~O.dirichlet_mask(N))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = 20000
-    sample = free[np.unique(rng.integers(0, len(free), size=n))]
     t0 = time.perf_counter()
-    O.apply_rows(N, x_canon, sample, kind=oracle.LSQP, q=q, coeffs=coeffs)
-    dt = time.perf_counter() - t0
-    n2 = int(min(len(free), max(n, n * budget_s / max(dt, 1e-6))))
-    sample = free[np.unique(rng.integers(0, len(free), size=n2))]
-    n2 = len(sample)
-    t0 = time.perf_counter()
-    O.apply_rows(N, x_canon, sample, kind=oracle.LSQP, q=q, coeffs=coeffs)
-    dt = time.perf_counter() - t0
-    return {"value": round(n2 / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads,
+    passes = 0
+    while True:
+        O.apply_rows(N, x_canon, free, kind=oracle.LSQP, q=q, coeffs=coeffs)
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or passes >= 8:
+            break
+    return {"value": round(len(free) * passes / dt / 1e9, 6), "unit": "GDoF/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d of %d free rows (uniform random, seed 123) of the same operator and "
-                      "input, oracle surrogate rows (Horner-free direct polynomial evaluation) "
-                      "and element-wise lower-primitive rows; %.1f s wall" % (n2, n_free_total, dt)}
+            "sample": "all %d free rows of the same operator and input, %d pass(es): oracle "
+                      "surrogate rows (direct evaluation of the 3D polynomials) and element-wise "
+                      "lower-primitive rows; %.1f s wall" % (n_free_total, passes, dt)}
+
+
+def solve_bench(ts, G, lam, op, log):
+    """V(3,3) solves of the manufactured problem to 1e-10 in three precisions
+    (the first solve of each allocates the hierarchy and is not timed)."""
+    import torch
+    fb = G.rhs(lam, ts.TS_RHS_MANUFACTURED, [0.55, 1.0])
+    out = {}
+    u64 = None
+    for prec, name in ((ts.TS_F64, "fp64"), (ts.TS_F32, "fp32_ir"), (ts.TS_F16W, "fp16w_ir")):
+        sv = ts.Solver(op, lam, precision=prec, rtol=1e-10, max_cycles=100)
+        u, rc, info = sv.solve(fb, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, rc, info = sv.solve(fb, raise_on_fail=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"ms": round(dt * 1e3, 2), "cycles": info.cycles, "status": rc,
+               "rel_residual": info.rel_residual, "ms_per_cycle": round(dt * 1e3 / max(info.cycles, 1), 3)}
+        if u64 is None:
+            u64 = u
+        else:
+            rec["max_rel_diff_vs_fp64_solve"] = float((u - u64).abs().max() / u64.abs().max())
+        out[name] = rec
+        log("solve %s: %s" % (name, rec))
+        del sv
+    out["fp32_ir_speedup_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
+    return out
+
+
+def serve_bench(n_requests, log):
+    from paper_1608_06473_amd import inputs
+    from paper_1608_06473_amd.serve import Server
+    trace = inputs.serving_trace(n_requests, rate=50.0, seed=0)
+    srv = Server(topology="shell288", max_active=32)
+    reqs, summ = srv.run(trace)
+    srv.close()
+    summ["trace"] = ("first %d requests of the Poisson(50/s) trace, levels 4-7, r_in ~ U[0.4, 0.7], "
+                     "8 Gaussian bumps, FP32 V(3,3) + FP64 refinement to 1e-8, 288-macro shell "
+                     "topology" % n_requests)
+    log("serving: %s" % json.dumps(summ))
+    return summ
 
 
 def main():
@@ -89,6 +168,9 @@ def main():
                     help="time only the surrogate volume kernel (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=30)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -178,23 +260,39 @@ def main():
                          "volume_gbs": round(alg_bytes / (q4_vol / 1e3) / 1e9, 1)}
     log("q=4 apply: %.3f ms (volume %.3f ms)" % (q4_ms, q4_vol))
     del op4
-    # FP32 apply and one Gauss-Seidel sweep (FP64)
+    # FP32 and FP16-weight applies, residual, Gauss-Seidel sweeps
     x32 = xb.float()
     y32 = torch.zeros_like(x32)
     ts.ts_apply(op.h, lam, ts.TS_F32, x32, y32, stream)
     f32_ms = time_events(lambda: ts.ts_apply(op.h, lam, ts.TS_F32, x32, y32, stream), reps, stream)
     extra["fp32_apply"] = {"ms": round(f32_ms, 4), "gdofs": round(info.n_free / f32_ms / 1e6, 3)}
-    del x32, y32
+    ts.ts_apply(op.h, lam, ts.TS_F16W, x32, y32, stream)
+    f16_ms = time_events(lambda: ts.ts_apply(op.h, lam, ts.TS_F16W, x32, y32, stream), reps, stream)
+    extra["fp16w_apply"] = {"ms": round(f16_ms, 4), "gdofs": round(info.n_free / f16_ms / 1e6, 3)}
     fb = G.rhs(lam, ts.TS_RHS_MANUFACTURED, [0.55, 1.0])
-    ub = torch.zeros_like(fb)
+    ub = xb.clone()
+    rb = G.zeros(lam)
+    res_ms = time_events(lambda: ts.ts_residual(op.h, lam, ts.TS_F64, fb, ub, rb, stream), reps,
+                         stream)
+    extra["residual"] = {"ms": round(res_ms, 4), "gdofs": round(info.n_free / res_ms / 1e6, 3)}
     gs_ms = time_events(lambda: ts.ts_smooth(op.h, lam, ts.TS_F64, fb, ub, 1, stream), 3, stream)
-    extra["gs_sweep"] = {"ms": round(gs_ms, 4), "gdofs": round(info.n_free / gs_ms / 1e6, 3)}
-    log("FP32 apply %.3f ms; GS sweep %.3f ms" % (f32_ms, gs_ms))
+    f32b, u32 = fb.float(), ub.float()
+    gs32_ms = time_events(lambda: ts.ts_smooth(op.h, lam, ts.TS_F32, f32b, u32, 1, stream), 3,
+                          stream)
+    extra["gs_sweep"] = {"ms": round(gs_ms, 4), "gdofs": round(info.n_free / gs_ms / 1e6, 3),
+                         "fp32_ms": round(gs32_ms, 4)}
+    log("FP32 apply %.3f ms, FP16W apply %.3f ms, residual %.3f ms, GS sweep %.3f ms (FP32 %.3f)"
+        % (f32_ms, f16_ms, res_ms, gs_ms, gs32_ms))
+    del x32, y32, f32b, u32, ub, rb, fb
+    if not args.no_solve:
+        extra["solve"] = solve_bench(ts, G, lam, op, log)
+    if not args.no_serve:
+        extra["serving"] = serve_bench(args.serve_requests, log)
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle on host cores)...")
-        cpu = cpu_baseline(vtx, tet, lam, q, op.coeffs(lam), x_canon, info.n_free)
+        cpu = cpu_baseline(vtx, tet, lam, q, x_canon, info.n_free)
         log("cpu baseline: %s" % cpu)
 
     line = {
@@ -216,9 +314,11 @@ def main():
                    "volume_dof": int(info.n_volume), "setup_s": round(t_setup, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_surrogate<2,double,double,0,0>",
+                     "traffic": pmc_traffic(),
+                     "kernel": "k_surr_lds<SurrogateW<2,double,0>,double,double,0,16,2>",
                      "kernel_ms": round(vol_ms, 4),
-                     "algorithmic_bytes": int(alg_bytes)},
+                     "algorithmic_bytes": int(alg_bytes),
+                     "kernel_source_hash": kernel_source_hash()},
         "cpu_baseline": cpu,
     }
     line.update(extra)

@@ -23,9 +23,9 @@ static void run(const Level& L, int nt, const int* ml, const float* cf, const do
     T* yp = (T*)y;
     const T* fp = (const T*)f;
     if (mode == 0)
-        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.gs_lanes.p, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.N, L.B, colour);
     else if (mode == 1)
-        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.gs_lanes.p, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.N, L.B, colour);
     else
         k_surr_lds<WP, T, W, 2, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(yp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.gs_lanes.p, L.N, L.B, colour);
 }

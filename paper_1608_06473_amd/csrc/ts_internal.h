@@ -118,6 +118,7 @@ struct Level {
     int n_lds_tiles = 0;
     int lds_kpt = 0;              // staged values per thread and plane
     DBuf<unsigned> gs_lanes;      // per tile and lane: i | j << 16 (GS order)
+    DBuf<unsigned> ap_lanes;      // per tile and lane: i | j << 16 (apply order)
     // fast path for free nodes of interior faces (exactly two copies): node
     // ids, both copies, and their combined rows as struct of arrays
     // [slot][face node] so that lane loads are coalesced; the remaining free
@@ -146,13 +147,16 @@ struct Level {
 };
 
 #ifndef TS_VOL_R
-#define TS_VOL_R 16
+#define TS_VOL_R 24
 #endif
 #ifndef TS_VOL_WAVES
 #define TS_VOL_WAVES 2
 #endif
 #ifndef TS_VOL_PF
 #define TS_VOL_PF 4
+#endif
+#ifndef TS_VOL_G
+#define TS_VOL_G 2
 #endif
 constexpr int VOL_R = TS_VOL_R;  // planes per volume tile
 constexpr int VOL_THREADS = 256;

@@ -240,16 +240,39 @@ struct SurrogateHalfW {
     }
 };
 
-// Branch-free staging loads: entries past the plane's range read a valid
-// in-block address (their LDS copies are never used by a live step).
+// Raw buffer accesses over one macro block: a resource with the block's base
+// and size, and a 32-bit byte offset per lane.  The hardware checks every
+// offset against the size: reads at or past it return 0 and writes there are
+// dropped, so no lane can touch memory outside its macro block.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+// Staging loads of one plane range: KPT consecutive entries per lane from
+// element g0 on; entries past the range are never used by a live step (and
+// read 0 past the block's end).
 template <typename T, int KPT>
-__device__ __forceinline__ void stage_load(const T* __restrict__ xm, int g0, int cnt, T r[KPT]) {
+__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g0, int cnt, T r[KPT]) {
     const int g = cnt > 0 ? g0 : 0;
 #pragma unroll
-    for (int s = 0; s < KPT; s++) {
-        const int e = (int)threadIdx.x + s * VOL_THREADS;
-        r[s] = xm[g + (e < cnt ? e : 0)];
-    }
+    for (int s = 0; s < KPT; s++)
+        r[s] = bload<T>(rx, (g + (int)threadIdx.x + s * VOL_THREADS) * (int)sizeof(T));
 }
 
 // WP: weight provider (SurrogateW or SurrogateHalfW), T: vector type, W:
@@ -258,48 +281,41 @@ template <class WP, typename T, typename W, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS)
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
-                int nt, const int* __restrict__ mlist, const unsigned* __restrict__ gs_lanes,
+                int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
                 int N, int64_t B, int colour) {
     constexpr int PF = TS_VOL_PF;
     int macro, tile;
     if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
     const int4 td = tiles[tile];
-    const int k0 = td.x, j0 = td.y, j1 = td.z, i0 = td.w;
-    const int Mr = N - 1 - k0;
+    const int k0 = td.x, j0 = td.y, j1 = td.z;
     const int tid = (int)threadIdx.x;
     // lanes without a column park at (1, j0): every index they form below
     // stays inside the staged range, so reads need no guard
     int i = 1, j = j0;
     bool act;
-    if (MODE == 2) {
-        // colour-class order of the tile's columns
-        const unsigned e = gs_lanes[(size_t)tile * VOL_THREADS + tid];
+    {
+        // column order of the tile (Gauss-Seidel: by colour class first)
+        const unsigned e = lanes[(size_t)tile * VOL_THREADS + tid];
         act = e != 0xFFFFFFFFu;
         if (act) {
             i = (int)(e & 0xFFFFu);
             j = (int)(e >> 16);
         }
-    } else if (i0 > 0) {
-        i = i0 + tid;
-        act = i <= Mr - j0;
-        if (!act) i = 1;
-    } else {
-        const int S0 = (j0 - 1) * (2 * Mr - j0) / 2;
-        const int S1 = (j1 - 1) * (2 * Mr - j1) / 2;
-        const int pos = S0 + tid;
-        act = pos < S1;
-        if (act) pos_to_ij(pos, Mr, i, j);
     }
     // number of live steps of this lane's column in the slab
     const int nlive = act ? min(N - 1 - i - j, k0 + R - 1) - k0 + 1 : 0;
     WP wp;
     wp.init_from(coef_f, coef_d, macro, N, i, j);
 
-    __shared__ T buf[2][KPT * VOL_THREADS];
+    // G planes are staged per barrier into one half of 2G plane buffers; a
+    // buffer is rewritten two groups later, after the next group's barrier
+    constexpr int G = TS_VOL_G;
+    __shared__ T buf[2 * G][KPT * VOL_THREADS];
     const size_t base = (size_t)macro * B;
-    const T* xm = x + base;
-    T* ym = y + base;
-    const T* fm = f ? f + base : nullptr;
+    const int64_t bbytes = B * (int64_t)sizeof(T);
+    const __amdgpu_buffer_rsrc_t rx = block_rsrc(x + base, bbytes);
+    const __amdgpu_buffer_rsrc_t ry = block_rsrc(y + base, bbytes);
+    const __amdgpu_buffer_rsrc_t rf = block_rsrc(f ? f + base : x + base, bbytes);
 
     // Incremental state.  Plane p has side A = N + 1 - p and po(p) points
     // before it; po(p + 1) = po(p) + A (A + 1) / 2.  The staged range of
@@ -319,7 +335,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
         const int jl = min(j1, N - p);
         const int nr = jl - jb + 1;
         const int cnt = (p <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
-        stage_load<T, KPT>(xm, po_pf + jb * A - jtri, cnt, pf[d]);
+        stage_load<T, KPT>(rx, po_pf + jb * A - jtri, cnt, pf[d]);
         po_pf += A * (A + 1) / 2;
     }
     int A0 = N + 2 - k0;                 // side of plane k0 - 1
@@ -341,7 +357,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
         const int r0 = (3 * (colour - col)) & 3;  // col + 3 r = colour (mod 4)
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            if ((r & 3) == r0) fg[r >> 2] = r < nlive ? fm[idf] : (T)0;
+            if ((r & 3) == r0) fg[r >> 2] = r < nlive ? bload<T>(rf, idf * (int)sizeof(T)) : (T)0;
             const int Af = N + 1 - (k0 + r);
             idf += Af * (Af + 1) / 2 - j;
         }
@@ -349,28 +365,34 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     if constexpr (MODE == 1) {
 #pragma unroll
         for (int d = 0; d < PF; d++) {
-            fr[d] = d < nlive ? fm[idf] : (T)0;
+            fr[d] = d < nlive ? bload<T>(rf, idf * (int)sizeof(T)) : (T)0;
             const int Af = N + 1 - (k0 + d);
             idf += Af * (Af + 1) / 2 - j;
         }
     }
     T pm[7], p0[7], pp[7];
 #pragma unroll
-    for (int st = 0; st < R + 2; st++) {
+    for (int g0 = 0; g0 < R + 2; g0 += G) {
+#pragma unroll
+    for (int st = g0; st < g0 + G && st < R + 2; st++) {
         const int p = k0 - 1 + st;
-        T* bb = buf[st & 1];
+        T* bb = buf[st % (2 * G)];
 #pragma unroll
         for (int s2 = 0; s2 < KPT; s2++) bb[tid + s2 * VOL_THREADS] = pf[st % PF][s2];
-        __syncthreads();
         if (st + PF <= R + 1) {
             const int pq = p + PF;
             const int A = N + 1 - pq;
             const int jl = min(j1, N - pq);
             const int nr = jl - jb + 1;
             const int cnt = (pq <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
-            stage_load<T, KPT>(xm, po_pf + jb * A - jtri, cnt, pf[st % PF]);
+            stage_load<T, KPT>(rx, po_pf + jb * A - jtri, cnt, pf[st % PF]);
             po_pf += A * (A + 1) / 2;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = g0; st < g0 + G && st < R + 2; st++) {
+        const T* bb = buf[st % (2 * G)];
         // the 7 points of plane p: (i,j) c, (i-1,j), (i+1,j), (i,j-1) c-qa-1,
         // (i+1,j-1), (i,j+1) c+qa, (i-1,j+1)
         {
@@ -393,7 +415,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
                     W sw[NW];
                     wp.weights_z(z, sw);
                     const T off = off_sum<T, W>(sw, pm, p0, pp);
-                    ym[idx] = (fg[r >> 2] - off) / (T)sw[0];
+                    bstore<T>(ry, idx * (int)sizeof(T), (fg[r >> 2] - off) / (T)sw[0]);
                 }
                 col = (col + 3) & 3;
             } else {
@@ -402,11 +424,11 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
                 const T off = off_sum<T, W>(sw, pm, p0, pp);
                 const T v = (T)sw[0] * p0[0] + off;
                 if (MODE == 0) {
-                    if (live) ym[idx] = v;
+                    if (live) bstore<T>(ry, idx * (int)sizeof(T), v);
                 } else {
-                    if (live) ym[idx] = fr[r % PF] - v;
+                    if (live) bstore<T>(ry, idx * (int)sizeof(T), fr[r % PF] - v);
                     if (r + PF < R) {
-                        fr[r % PF] = r + PF < nlive ? fm[idf] : (T)0;
+                        fr[r % PF] = r + PF < nlive ? bload<T>(rf, idf * (int)sizeof(T)) : (T)0;
                         const int Af = N + 1 - (k0 + r + PF);
                         idf += Af * (Af + 1) / 2 - j;
                     }
@@ -423,6 +445,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
             pm[q] = p0[q];
             p0[q] = pp[q];
         }
+    }
     }
 }
 

@@ -342,14 +342,21 @@ Level& Mesh::level(int lam) {
     L->lds_tiles.upload(lt);
     L->n_lds_tiles = (int)lt.size();
     L->lds_kpt = (int)((maxcnt + VOL_THREADS - 1) / VOL_THREADS);
-    // Gauss-Seidel lane order: the columns of every tile sorted (stably) by
-    // (i + 2j) mod 4, so that a wavefront holds one colour class per plane
-    // and skips the planes where its class is not being updated
+    // Lane orders of the columns of every tile.  Columns with i + j above
+    // N - k0 - R end inside the slab; sorting them after the others (by
+    // i + j) gathers the columns that have ended into whole wavefronts, which
+    // then skip their weight evaluation.  Apply order: the full-length
+    // columns row by row, then the ending ones.  Gauss-Seidel order: first
+    // by colour class (i + 2j) mod 4, so that a wavefront holds one class
+    // per plane and skips the planes where its class is not updated, then
+    // as in the apply order.
     {
-        std::vector<unsigned> lm((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
+        std::vector<unsigned> am((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
+        std::vector<unsigned> gm((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
         for (size_t t = 0; t < lt.size(); t++) {
             const int4 d = lt[t];
             const int Mr = N - 1 - d.x;
+            const int full = N - d.x - VOL_R;  // i + j <= full: column spans the slab
             std::vector<std::pair<int, int>> pos;
             if (d.w > 0) {
                 for (int i = d.w; i <= std::min(d.w + VOL_THREADS - 1, Mr - d.y); i++)
@@ -358,14 +365,26 @@ Level& Mesh::level(int lam) {
                 for (int j = d.y; j < d.z; j++)
                     for (int i = 1; i <= Mr - j; i++) pos.push_back({i, j});
             }
-            std::stable_sort(pos.begin(), pos.end(), [](const std::pair<int, int>& a,
-                                                        const std::pair<int, int>& b) {
-                return ((a.first + 2 * a.second) & 3) < ((b.first + 2 * b.second) & 3);
+            auto band = [&](const std::pair<int, int>& a) {
+                return std::max(a.first + a.second, full);
+            };
+            auto cls = [](const std::pair<int, int>& a) { return (a.first + 2 * a.second) & 3; };
+            std::vector<std::pair<int, int>> ap(pos), gs(pos);
+            std::stable_sort(ap.begin(), ap.end(), [&](const std::pair<int, int>& a,
+                                                       const std::pair<int, int>& b) {
+                return band(a) < band(b);
             });
-            for (size_t l = 0; l < pos.size(); l++)
-                lm[t * VOL_THREADS + l] = (unsigned)pos[l].first | ((unsigned)pos[l].second << 16);
+            std::stable_sort(gs.begin(), gs.end(), [&](const std::pair<int, int>& a,
+                                                       const std::pair<int, int>& b) {
+                return cls(a) != cls(b) ? cls(a) < cls(b) : band(a) < band(b);
+            });
+            for (size_t l = 0; l < pos.size(); l++) {
+                am[t * VOL_THREADS + l] = (unsigned)ap[l].first | ((unsigned)ap[l].second << 16);
+                gm[t * VOL_THREADS + l] = (unsigned)gs[l].first | ((unsigned)gs[l].second << 16);
+            }
         }
-        L->gs_lanes.upload(lm);
+        L->ap_lanes.upload(am);
+        L->gs_lanes.upload(gm);
     }
     // all-slot tiles: every plane k = 0..N in chunks of 256 slots
     std::vector<int2> st;

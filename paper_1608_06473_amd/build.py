@@ -17,6 +17,8 @@ LIB = os.path.join(HERE, "libtwoscale.so")
 SOURCES = ["ts_topology.cpp", "ts_api.cpp", "k_stencil.hip", "k_misc.hip"]
 # the surrogate volume kernel, one unit per (degree q, staging width kpt)
 INST = [(q, k) for q in (1, 2, 3, 4) for k in (2, 4, 8)]
+# the IFEM volume kernel, one unit per staging width (levels up to 8)
+IFEM_KPT = (2, 4)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -38,6 +40,8 @@ def build(jobs=8, verbose=True, lib_path=LIB, defines=(), build_dir=None):
     units = [(s, os.path.join(bdir, os.path.splitext(s)[0] + ".o"), []) for s in SOURCES]
     units += [("k_surr_inst.hip", os.path.join(bdir, "k_surr_q%d_k%d.o" % (q, k)),
                ["TS_Q=%d" % q, "TS_KPT=%d" % k]) for q, k in INST]
+    units += [("k_ifem.hip", os.path.join(bdir, "k_ifem_k%d.o" % k), ["TS_KPT=%d" % k])
+              for k in IFEM_KPT]
     objs = [u[1] for u in units]
     procs = []
     for src, obj, extra in units:

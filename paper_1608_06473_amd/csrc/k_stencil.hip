@@ -10,112 +10,6 @@
 
 namespace ts {
 
-// The 7 points (i,j), (i-1,j), (i+1,j), (i,j-1), (i,j+1), (i+1,j-1), (i-1,j+1)
-// of plane p.  c is the block index of (i, j, p) and A = N + 1 - p the side
-// of plane p (row j holds A - j points), so row j-1 starts A - j + 1 points
-// before row j and row j+1 starts A - j points after it.  The two points with
-// index sum i + j + 1 exist only if i + j + 2 <= A.
-template <typename T>
-__device__ __forceinline__ void load7(const T* xm, int c, int A, int i, int j, T o[7]) {
-    const bool hi = i + j + 2 <= A;
-    const int rs = c - (A - j + 1);
-    const int rn = c + (A - j);
-    o[0] = xm[c];
-    o[1] = xm[c - 1];
-    o[2] = hi ? xm[c + 1] : (T)0;
-    o[3] = xm[rs];
-    o[4] = hi ? xm[rn] : (T)0;
-    o[5] = xm[rs + 1];
-    o[6] = xm[rn - 1];
-}
-
-// IFEM: the exact stencil from the 24 fine tetrahedra at the node.
-struct IfemW {
-    MacroGeom g;
-    int N, i, j;
-    __device__ __forceinline__ void weights(int k, double s[NW]) const {
-        ifem_partial_stencil(g, N, i, j, k, s);
-    }
-};
-
-// Volume kernel body ----------------------------------------------------------
-// MODE 0: y = L x; 1: y = f - L x; 2: Gauss-Seidel update of colour `colour`
-// in place (x == y).  Block indices advance incrementally: from plane p to
-// p + 1 the index of (i, j) grows by T(A) - j with T(A) = A (A + 1) / 2 the
-// size of plane p and A = N + 1 - p.
-template <typename T, typename W, int MODE, int R, class WP>
-__device__ __forceinline__ void volume_body(const T* xm, T* ym, const T* fm, WP& wp, int N,
-                                            int i, int j, int k0, int kend, int colour) {
-    T pm[7], p0[7], pp[7];
-    int A = N + 2 - k0;  // side of plane k0 - 1
-    int c = (int)bidx(N, i, j, k0 - 1);
-    load7(xm, c, A, i, j, pm);
-    c += A * (A + 1) / 2 - j;
-    A -= 1;
-    load7(xm, c, A, i, j, p0);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int k = k0 + r;
-        if (k > kend) break;
-        const int cn = c + A * (A + 1) / 2 - j;
-        load7(xm, cn, A - 1, i, j, pp);
-        if (MODE == 2) {
-            if (((i + 2 * j + 3 * k) & 3) == colour) {
-                W s[NW];
-                wp.weights(k, s);
-                const T off = off_sum<T, W>(s, pm, p0, pp);
-                ym[c] = (fm[c] - off) / (T)s[0];
-            }
-        } else {
-            W s[NW];
-            wp.weights(k, s);
-            const T v = (T)s[0] * p0[0] + off_sum<T, W>(s, pm, p0, pp);
-            if (MODE == 0)
-                ym[c] = v;
-            else
-                ym[c] = fm[c] - v;
-        }
-#pragma unroll
-        for (int q = 0; q < 7; q++) {
-            pm[q] = p0[q];
-            p0[q] = pp[q];
-        }
-        c = cn;
-        A -= 1;
-    }
-}
-
-template <typename T, int MODE, int R>
-__global__ __launch_bounds__(VOL_THREADS) void k_ifem_volume(
-    const T* x, T* y, const T* __restrict__ f, const MacroGeom* __restrict__ geom,
-    const int2* __restrict__ tiles, int n_tiles, int nt, const int* __restrict__ mlist,
-    const unsigned* __restrict__ gs_lanes, int N, int64_t B, int colour) {
-    int macro, tile;
-    if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
-    const int2 td = tiles[tile];
-    const int k0 = td.x, Mr = N - 1 - k0;
-    int i, j;
-    if (MODE == 2) {  // colour-class lane order
-        const unsigned e = gs_lanes[(size_t)tile * VOL_THREADS + threadIdx.x];
-        if (e == 0xFFFFFFFFu) return;
-        i = (int)(e & 0xFFFFu);
-        j = (int)(e >> 16);
-    } else {
-        const int pos = td.y + (int)threadIdx.x;
-        if (pos >= (Mr - 1) * Mr / 2) return;
-        pos_to_ij(pos, Mr, i, j);
-    }
-    const int kend = min(N - 1 - i - j, k0 + R - 1);
-    IfemW wp;
-    wp.g = geom[macro];
-    wp.N = N;
-    wp.i = i;
-    wp.j = j;
-    const size_t base = (size_t)macro * B;
-    volume_body<T, double, MODE, R>(x + base, y + base, f ? f + base : nullptr, wp, N, i, j, k0,
-                                 kend, colour);
-}
-
 // Lower primitives -------------------------------------------------------------
 // Block-index offsets of the 15 stencil neighbours of the node at block index
 // base = (i, j, k), from its row j and the side A = N + 1 - k of its plane:
@@ -381,10 +275,6 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
 
 // Launchers --------------------------------------------------------------------
 
-static int grid_volume(const Level& L, int64_t nt) {
-    return (int)(((nt + 7) / 8) * 8 * L.n_tiles);
-}
-
 #define TS_DECL(Q, K)                                                                     \
     void launch_surr_q##Q##_k##K(const Level& L, int nt, const LevelOp& lo, int dtype,    \
                                  int center, int mode, const void* x, void* y,            \
@@ -427,32 +317,34 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     TS_HIP(hipGetLastError());
 }
 
-template <typename T>
-static void run_ifem_volume(const Mesh& M, const Level& L, int mode, const void* x, void* y,
-                            const void* f, int colour, hipStream_t s, const int* ml, int nt) {
-    const dim3 grid(grid_volume(L, nt)), blk(VOL_THREADS);
-    if (grid.x == 0) return;
-    const T* xp = (const T*)x;
-    T* yp = (T*)y;
-    const T* fp = (const T*)f;
-    if (mode == 0)
-        k_ifem_volume<T, 0, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
-    else if (mode == 1)
-        k_ifem_volume<T, 1, VOL_R><<<grid, blk, 0, s>>>(xp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
-    else
-        k_ifem_volume<T, 2, VOL_R><<<grid, blk, 0, s>>>(yp, yp, fp, M.d_geom.p, L.tiles.p, L.n_tiles, nt, ml, L.gs_lanes_ifem.p, L.N, L.B, colour);
+void launch_ifem_k2(const Level& L, const double* xyz, int nt, const int* mlist, int dtype,
+                    int mode, const void* x, void* y, const void* f, int colour, hipStream_t s);
+void launch_ifem_k4(const Level& L, const double* xyz, int nt, const int* mlist, int dtype,
+                    int mode, const void* x, void* y, const void* f, int colour, hipStream_t s);
+
+// blended coordinates of every slot of a level, computed on first use
+static const double* level_coords(Mesh& M, int lam, hipStream_t s) {
+    Level& L = M.level(lam);
+    if (!L.xyz.p) {
+        L.xyz.alloc((size_t)3 * L.len);
+        launch_coords(M, lam, L.xyz.p, s);
+    }
+    return L.xyz.p;
 }
 
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                         const void* f, int colour, hipStream_t s, const int* mlist, int n_list) {
-    const Mesh& M = op->mesh->m;
-    const Level& L = const_cast<Mesh&>(M).level(lam);
+    Mesh& M = op->mesh->m;
+    const Level& L = M.level(lam);
     const int nt = n_list >= 0 ? n_list : (int)M.nt;
-    if (nt == 0) return;
-    if (dtype == TS_F64)
-        run_ifem_volume<double>(M, L, mode, x, y, f, colour, s, mlist, nt);
+    if (nt == 0 || L.n_lds_tiles == 0) return;
+    TS_REQUIRE(L.lds_kpt <= 4, TS_EINVAL,
+               "element-wise (IFEM) volume rows are supported up to level 8");
+    const double* xyz = level_coords(M, lam, s);
+    if (L.lds_kpt <= 2)
+        launch_ifem_k2(L, xyz, nt, mlist, dtype, mode, x, y, f, colour, s);
     else
-        run_ifem_volume<float>(M, L, mode, x, y, f, colour, s, mlist, nt);
+        launch_ifem_k4(L, xyz, nt, mlist, dtype, mode, x, y, f, colour, s);
     TS_HIP(hipGetLastError());
 }
 

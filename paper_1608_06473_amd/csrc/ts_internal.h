@@ -105,10 +105,6 @@ struct Level {
     int n_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
     DBuf<int> if_free;            // free interface nodes (for norms)
     int n_if_free = 0;
-    // volume tiles: (k0, first position in plane k0's interior triangle)
-    DBuf<int2> tiles;
-    int n_tiles = 0;
-    DBuf<unsigned> gs_lanes_ifem;  // per tile and lane: i | j << 16 (GS order)
     // all-slot tiles: (plane k, first slot of a chunk of plane k)
     DBuf<int2> slot_tiles;
     int n_slot_tiles = 0;
@@ -119,6 +115,8 @@ struct Level {
     int lds_kpt = 0;              // staged values per thread and plane
     DBuf<unsigned> gs_lanes;      // per tile and lane: i | j << 16 (GS order)
     DBuf<unsigned> ap_lanes;      // per tile and lane: i | j << 16 (apply order)
+    DBuf<double> xyz;             // blended coordinates of every slot (x, y, z),
+                                  // built on the first element-wise volume pass
     // fast path for free nodes of interior faces (exactly two copies): node
     // ids, both copies, and their combined rows as struct of arrays
     // [slot][face node] so that lane loads are coalesced; the remaining free

@@ -274,38 +274,6 @@ Level& Mesh::level(int lam) {
         }
     }
 
-    // volume tiles: planes k0 = 1, 1 + R, ... with chunks of positions of the
-    // interior triangle of plane k0 (i, j >= 1, i + j <= N - 1 - k0)
-    std::vector<int2> tiles;
-    for (int k0 = 1; k0 <= N - 3; k0 += VOL_R) {
-        const int Mr = N - 1 - k0;
-        const int npos = (Mr - 1) * Mr / 2;
-        for (int s = 0; s < npos; s += VOL_THREADS) tiles.push_back(make_int2(k0, s));
-    }
-    L->tiles.upload(tiles);
-    L->n_tiles = (int)tiles.size();
-    // Gauss-Seidel lane order of these tiles: positions sorted (stably) by
-    // (i + 2j) mod 4 (one colour class per wavefront and plane)
-    {
-        std::vector<unsigned> lm((size_t)tiles.size() * VOL_THREADS, 0xFFFFFFFFu);
-        for (size_t t = 0; t < tiles.size(); t++) {
-            const int k0 = tiles[t].x, Mr = N - 1 - k0;
-            const int npos = (Mr - 1) * Mr / 2;
-            std::vector<std::pair<int, int>> pos;
-            int p = 0;
-            for (int j = 1; j <= Mr - 1; j++)
-                for (int i = 1; i <= Mr - j; i++, p++)
-                    if (p >= tiles[t].y && p < std::min(npos, tiles[t].y + VOL_THREADS))
-                        pos.push_back({i, j});
-            std::stable_sort(pos.begin(), pos.end(), [](const std::pair<int, int>& a,
-                                                        const std::pair<int, int>& b) {
-                return ((a.first + 2 * a.second) & 3) < ((b.first + 2 * b.second) & 3);
-            });
-            for (size_t l = 0; l < pos.size(); l++)
-                lm[t * VOL_THREADS + l] = (unsigned)pos[l].first | ((unsigned)pos[l].second << 16);
-        }
-        L->gs_lanes_ifem.upload(lm);
-    }
     // LDS-staged tiles: whole rows of plane k0's interior up to 256
     // positions, long rows split; the staged range of plane p covers rows
     // j0-1 .. j1 of that plane
@@ -329,8 +297,17 @@ Level& Mesh::level(int lam) {
                 j++;
                 continue;
             }
+            // whole rows while the tile stays within 256 columns and no
+            // colour class (i + 2j) mod 4 exceeds one wavefront of 64
             int j1 = j, tot = 0;
+            int cc[4] = {0, 0, 0, 0};
             while (j1 <= Mr - 1 && tot + (Mr - j1) <= VOL_THREADS) {
+                int add[4] = {0, 0, 0, 0};
+                for (int i = 1; i <= Mr - j1; i++) add[(i + 2 * j1) & 3]++;
+                bool fits = true;
+                for (int q = 0; q < 4; q++) fits = fits && cc[q] + add[q] <= VOL_THREADS / 4;
+                if (!fits && j1 > j) break;
+                for (int q = 0; q < 4; q++) cc[q] += add[q];
                 tot += Mr - j1;
                 j1++;
             }
@@ -346,10 +323,10 @@ Level& Mesh::level(int lam) {
     // N - k0 - R end inside the slab; sorting them after the others (by
     // i + j) gathers the columns that have ended into whole wavefronts, which
     // then skip their weight evaluation.  Apply order: the full-length
-    // columns row by row, then the ending ones.  Gauss-Seidel order: first
-    // by colour class (i + 2j) mod 4, so that a wavefront holds one class
-    // per plane and skips the planes where its class is not updated, then
-    // as in the apply order.
+    // columns row by row, then the ending ones.  Gauss-Seidel order: colour
+    // class (i + 2j) mod 4 = q in wavefront q (lanes 64q ..), so that a
+    // wavefront holds one class per plane and skips the planes where its
+    // class is not updated; within a class as in the apply order.
     {
         std::vector<unsigned> am((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
         std::vector<unsigned> gm((size_t)lt.size() * VOL_THREADS, 0xFFFFFFFFu);
@@ -378,9 +355,15 @@ Level& Mesh::level(int lam) {
                                                        const std::pair<int, int>& b) {
                 return cls(a) != cls(b) ? cls(a) < cls(b) : band(a) < band(b);
             });
+            int fill[4] = {0, 0, 0, 0};
             for (size_t l = 0; l < pos.size(); l++) {
                 am[t * VOL_THREADS + l] = (unsigned)ap[l].first | ((unsigned)ap[l].second << 16);
-                gm[t * VOL_THREADS + l] = (unsigned)gs[l].first | ((unsigned)gs[l].second << 16);
+                // class q takes the lanes of wavefront q (64 lanes; tiles keep
+                // every class within that)
+                const int q = cls(gs[l]);
+                const int lane = fill[q] < VOL_THREADS / 4 ? q * (VOL_THREADS / 4) + fill[q]++ : -1;
+                if (lane < 0) throw Error{TS_EINVAL, "volume tile with a colour class above 64"};
+                gm[t * VOL_THREADS + lane] = (unsigned)gs[l].first | ((unsigned)gs[l].second << 16);
             }
         }
         L->ap_lanes.upload(am);

@@ -315,7 +315,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": pmc_traffic(),
-                     "kernel": "k_surr_lds<SurrogateW<2,double,0>,double,double,0,16,2>",
+                     "kernel": "k_surr_lds (surrogate volume rows, FP64, apply)",
                      "kernel_ms": round(vol_ms, 4),
                      "algorithmic_bytes": int(alg_bytes),
                      "kernel_source_hash": kernel_source_hash()},

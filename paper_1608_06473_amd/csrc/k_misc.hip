@@ -235,21 +235,21 @@ __device__ __forceinline__ double block_sum(double v) {
     return sh[0];
 }
 
+// one workgroup per (plane k = 1 .. N-3, macro): the interior rows of the
+// plane are contiguous runs of the block layout
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x, const int2* __restrict__ slot_tiles,
-                                                     int N, int64_t B, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x, int N, int64_t B,
+                                                     double* __restrict__ partial) {
+    const int k = 1 + (int)blockIdx.x;
     const int macro = blockIdx.y;
-    const int2 td = slot_tiles[blockIdx.x];
-    const int k = td.x;
-    const int A = N + 1 - k;
-    const int r = td.y + (int)threadIdx.x;
+    const T* xm = x + (size_t)macro * B + plane_off(N, k);
     double v = 0.0;
-    if (r < A * (A + 1) / 2) {
-        int i, j;
-        plane_pos_to_ij(r, A, i, j);
-        if (i >= 1 && j >= 1 && k >= 1 && i + j + k <= N - 1) {
-            const double a = (double)x[(size_t)macro * B + plane_off(N, k) + r];
-            v = a * a;
+    for (int j = 1; j <= N - 2 - k; j++) {
+        const int64_t r0 = row_off(N, j, k);
+        const int len = N - 1 - j - k;  // i = 1 .. len
+        for (int i = 1 + (int)threadIdx.x; i <= len; i += 256) {
+            const double a = (double)xm[r0 + i];
+            v += a * a;
         }
     }
     const double s = block_sum(v);
@@ -272,32 +272,57 @@ __global__ __launch_bounds__(256) void k_norm_iface(const T* __restrict__ x, con
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int64_t n, double* out) {
+// tree reduction of partial sums in a fixed order: workgroup b sums
+// p[b * 4096 .. b * 4096 + 4095] (sqrt of the total when `root` and a single
+// workgroup)
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int64_t n,
+                                                      double* out, int root) {
+    const int64_t b0 = (int64_t)blockIdx.x * 4096;
     double v = 0.0;
-    for (int64_t t = threadIdx.x; t < n; t += 256) v += p[t];
+    for (int t = threadIdx.x; t < 4096; t += 256)
+        if (b0 + t < n) v += p[b0 + t];
     const double s = block_sum(v);
-    if (threadIdx.x == 0) out[0] = sqrt(s);
+    if (threadIdx.x == 0) out[blockIdx.x] = root ? sqrt(s) : s;
+}
+
+static int64_t volume_partials(const Mesh& M, int lam) {
+    const int N = 1 << lam;
+    return (int64_t)(N > 3 ? N - 3 : 0) * M.nt;
 }
 
 int64_t norm_partial_count(const Mesh& M, int lam) {
     const Level& L = const_cast<Mesh&>(M).level(lam);
-    return (int64_t)L.n_slot_tiles * M.nt + (L.n_if_free + 255) / 256 + 1;
+    const int64_t n = volume_partials(M, lam) + (L.n_if_free + 255) / 256;
+    // partials, then the sums of up to 4096 partials each, then their sums
+    return n + (n + 4095) / 4096 + 2;
 }
 
 void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
                        double* out, hipStream_t s) {
     const Level& L = const_cast<Mesh&>(M).level(lam);
-    const dim3 g1(L.n_slot_tiles, (unsigned)M.nt);
-    const int64_t n1 = (int64_t)L.n_slot_tiles * M.nt;
+    const int64_t n1 = volume_partials(M, lam);
     const int n2 = (L.n_if_free + 255) / 256;
-    if (dtype == TS_F64) {
-        k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.slot_tiles.p, L.N, L.B, partial);
-        if (n2) k_norm_iface<double><<<n2, 256, 0, s>>>((const double*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
-    } else {
-        k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.slot_tiles.p, L.N, L.B, partial);
-        if (n2) k_norm_iface<float><<<n2, 256, 0, s>>>((const float*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
+    if (n1) {
+        const dim3 g1((unsigned)(L.N - 3), (unsigned)M.nt);
+        if (dtype == TS_F64)
+            k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.N, L.B, partial);
+        else
+            k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.N, L.B, partial);
     }
-    k_sum_partials<<<1, 256, 0, s>>>(partial, n1 + n2, out);
+    if (n2) {
+        if (dtype == TS_F64)
+            k_norm_iface<double><<<n2, 256, 0, s>>>((const double*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
+        else
+            k_norm_iface<float><<<n2, 256, 0, s>>>((const float*)x, L.if_free.p, L.n_if_free, L.if_off.p, L.if_copy.p, L.N, L.B, partial + n1);
+    }
+    const int64_t n = n1 + n2;
+    const int64_t m = (n + 4095) / 4096;
+    double* mid = partial + n;
+    // n <= 4096^2 for every supported level and mesh of up to a few
+    // thousand macros, so two stages suffice
+    TS_REQUIRE(m <= 4096, TS_EINVAL, "too many partial sums for the norm");
+    k_sum_partials<<<(unsigned)m, 256, 0, s>>>(partial, n, mid, 0);
+    k_sum_partials<<<1, 256, 0, s>>>(mid, m, out, 1);
     TS_HIP(hipGetLastError());
 }
 
@@ -696,12 +721,28 @@ __global__ __launch_bounds__(256) void k_coarse_gather(const T* __restrict__ f, 
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) fb[r] = (double)f[slot[off[r]]];
 }
-__global__ __launch_bounds__(256) void k_coarse_matvec(const double* __restrict__ AinvT, const double* __restrict__ fb,
-                                                       int n, double* __restrict__ ub) {
+// ub = A^{-1} fb with the transposed inverse: workgroup (x, y) takes rows
+// 64x .. 64x+63 and the columns of split y (KSPLIT splits, 4 interleaved
+// column lanes each), partial sums summed in a fixed order afterwards
+constexpr int KSPLIT = 16;
+__global__ __launch_bounds__(256) void k_coarse_matvec(const double* __restrict__ AinvT,
+                                                       const double* __restrict__ fb, int n,
+                                                       double* __restrict__ part) {
+    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int lane = threadIdx.x >> 6;
+    const int per = (n + KSPLIT - 1) / KSPLIT;
+    const int c0 = blockIdx.y * per, c1 = min(n, c0 + per);
+    double s = 0.0;
+    if (r < n)
+        for (int c = c0 + lane; c < c1; c += 4) s += AinvT[(size_t)c * n + r] * fb[c];
+    if (r < n) part[((size_t)blockIdx.y * 4 + lane) * n + r] = s;
+}
+__global__ __launch_bounds__(256) void k_coarse_matvec_sum(const double* __restrict__ part, int n,
+                                                           double* __restrict__ ub) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     double s = 0.0;
-    for (int c = 0; c < n; c++) s += AinvT[(size_t)c * n + r] * fb[c];
+    for (int q = 0; q < KSPLIT * 4; q++) s += part[(size_t)q * n + r];
     ub[r] = s;
 }
 template <typename T>
@@ -721,15 +762,18 @@ void launch_coarse_solve(const double* AinvT, int n, const int* free_first, cons
     const int g = (n + 255) / 256;
     double* fb = work;
     double* ub = work + n;
-    if (dtype == TS_F64) {
+    double* part = work + 2 * (size_t)n;
+    const dim3 gm((unsigned)((n + 63) / 64), KSPLIT);
+    if (dtype == TS_F64)
         k_coarse_gather<double><<<g, 256, 0, s>>>((const double*)f, cp_off, cp_slot, n, fb);
-        k_coarse_matvec<<<g, 256, 0, s>>>(AinvT, fb, n, ub);
-        k_coarse_scatter<double><<<g, 256, 0, s>>>((double*)u, cp_off, cp_slot, n, ub);
-    } else {
+    else
         k_coarse_gather<float><<<g, 256, 0, s>>>((const float*)f, cp_off, cp_slot, n, fb);
-        k_coarse_matvec<<<g, 256, 0, s>>>(AinvT, fb, n, ub);
+    k_coarse_matvec<<<gm, 256, 0, s>>>(AinvT, fb, n, part);
+    k_coarse_matvec_sum<<<g, 256, 0, s>>>(part, n, ub);
+    if (dtype == TS_F64)
+        k_coarse_scatter<double><<<g, 256, 0, s>>>((double*)u, cp_off, cp_slot, n, ub);
+    else
         k_coarse_scatter<float><<<g, 256, 0, s>>>((float*)u, cp_off, cp_slot, n, ub);
-    }
     TS_HIP(hipGetLastError());
 }
 

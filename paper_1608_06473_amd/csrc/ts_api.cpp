@@ -294,7 +294,7 @@ static void coarse_setup(ts_solver* sv, hipStream_t s) {
     TS_HIP(hipGetLastError());
     sv->AinvT.alloc((size_t)n * n);
     launch_transpose(A.p, sv->AinvT.p, n, s);
-    sv->cwork.alloc(2 * (size_t)n);
+    sv->cwork.alloc((2 + 4 * 16) * (size_t)n);  // fb, ub and the matvec partial sums
     TS_HIP(hipStreamSynchronize(s));
 }
 

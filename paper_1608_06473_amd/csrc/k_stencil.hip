@@ -6,37 +6,12 @@
 // surrogate volume kernel.  Each kernel serves y = L x, r = f - L x and the
 // Gauss-Seidel update u_I = (f_I - sum_{w != mc} s_w u_{I_w}) / s_mc
 // (eq. iteration-scheme).
+#include "ts_face.h"
 #include "ts_surrogate.h"
 
 namespace ts {
 
 // Lower primitives -------------------------------------------------------------
-// Block-index offsets of the 15 stencil neighbours of the node at block index
-// base = (i, j, k), from its row j and the side A = N + 1 - k of its plane:
-// rows j-1 / j+1 start A - j + 1 points before / A - j points after row j;
-// plane k+1 starts T(A) - j points after (i, j, k) (T(A) = A (A + 1) / 2) and
-// plane k-1 ends T(A + 1) - j points before it.
-__device__ __forceinline__ void nbr_index(int base, int A, int j, int o[NW]) {
-    const int rs = base - (A - j + 1), rn = base + (A - j);
-    const int bm = base - (A + 1) * (A + 2) / 2 + j;
-    const int tp = base + A * (A + 1) / 2 - j;
-    o[0] = base;
-    o[1] = base - 1;
-    o[2] = base + 1;
-    o[3] = rs;
-    o[4] = rn;
-    o[5] = rs + 1;
-    o[6] = rn - 1;
-    o[7] = bm;
-    o[8] = bm + 1;
-    o[9] = bm + (A + 1 - j);
-    o[10] = bm + (A - j);
-    o[11] = tp;
-    o[12] = tp - 1;
-    o[13] = tp - (A - j);
-    o[14] = tp - (A - j) + 1;
-}
-
 // General path: one thread per listed free face/edge/vertex node, summing
 // over the node's copies the stored element-wise partial stencil of each
 // adjacent macro.  MODE 0: y = L x; 1: y = f - L x, written to every copy;
@@ -99,54 +74,6 @@ __global__ __launch_bounds__(256) void k_zero_slots(T* __restrict__ y,
     if (t < n) y[slots[t]] = (T)0;
 }
 
-// Face path: free nodes of interior faces, each with exactly two copies A
-// and B.  A face node of macro A lies on one of its faces: i = 0, j = 0,
-// k = 0 or i + j + k = N (face type 0..3).  Of the 15 directions, 7 stay in
-// the face, 4 point into the macro and 4 out of it.  The node's row is stored
-// once per level as 15 combined weights (struct of arrays [15][n2]): slots
-// 0..10 the non-outward directions of A in increasing order (in-face weights
-// summed over both sides), slots 11..14 the inward directions of B.
-struct FaceDirs {
-    int a[4][11];  // non-outward directions of a copy on face type f
-    int b[4][4];   // inward directions
-};
-constexpr int kDI[NW] = {0, -1, 1, 0, 0, 1, -1, 0, 1, 0, -1, 0, -1, 0, 1};
-constexpr int kDJ[NW] = {0, 0, 0, -1, 1, -1, 1, 0, 0, 1, 1, 0, 0, -1, -1};
-constexpr int kDK[NW] = {0, 0, 0, 0, 0, 0, 0, -1, -1, -1, -1, 1, 1, 1, 1};
-// signed distance of direction w from face type f (< 0 outward, > 0 inward)
-constexpr int face_side(int f, int w) {
-    return f == 0 ? kDI[w] : f == 1 ? kDJ[w] : f == 2 ? kDK[w] : -(kDI[w] + kDJ[w] + kDK[w]);
-}
-constexpr FaceDirs make_face_dirs() {
-    FaceDirs d{};
-    for (int f = 0; f < 4; f++) {
-        int na = 0, nb = 0;
-        for (int w = 0; w < NW; w++) {
-            if (face_side(f, w) >= 0) d.a[f][na++] = w;
-            if (face_side(f, w) > 0) d.b[f][nb++] = w;
-        }
-    }
-    return d;
-}
-inline constexpr FaceDirs kFaceDirs = make_face_dirs();
-
-__device__ __forceinline__ int face_type(int N, int i, int j, int k) {
-    return i == 0 ? 0 : j == 0 ? 1 : k == 0 ? 2 : 3;
-}
-
-template <int F, typename T>
-__device__ __forceinline__ void face_acc_a(const double* __restrict__ sw, int n2, const T* xm,
-                                           const int o[NW], double& of) {
-#pragma unroll
-    for (int e = 1; e < 11; e++) of += sw[(size_t)e * n2] * (double)xm[o[kFaceDirs.a[F][e]]];
-}
-template <int F, typename T>
-__device__ __forceinline__ void face_acc_b(const double* __restrict__ sw, int n2, const T* xm,
-                                           const int o[NW], double& of) {
-#pragma unroll
-    for (int e = 0; e < 4; e++) of += sw[(size_t)(11 + e) * n2] * (double)xm[o[kFaceDirs.b[F][e]]];
-}
-
 // Same modes as k_iface; list (optional) selects positions.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_face2(
@@ -155,38 +82,7 @@ __global__ __launch_bounds__(256) void k_face2(
     const int* __restrict__ list, int n, int N, int64_t B, double* __restrict__ tmp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int q = list ? list[t] : t;
-    const int4 ca = cp[q], cb = cp[(size_t)n2 + q];
-    const int ba = (int)bidx(N, ca.y, ca.z, ca.w), bb = (int)bidx(N, cb.y, cb.z, cb.w);
-    const T* xa = x + (size_t)ca.x * B;
-    const T* xb = x + (size_t)cb.x * B;
-    const double* sw = sten + q;
-    int o[NW];
-    double of = 0.0;
-    nbr_index(ba, N + 1 - ca.w, ca.z, o);
-    switch (face_type(N, ca.y, ca.z, ca.w)) {
-        case 0: face_acc_a<0>(sw, n2, xa, o, of); break;
-        case 1: face_acc_a<1>(sw, n2, xa, o, of); break;
-        case 2: face_acc_a<2>(sw, n2, xa, o, of); break;
-        default: face_acc_a<3>(sw, n2, xa, o, of); break;
-    }
-    nbr_index(bb, N + 1 - cb.w, cb.z, o);
-    switch (face_type(N, cb.y, cb.z, cb.w)) {
-        case 0: face_acc_b<0>(sw, n2, xb, o, of); break;
-        case 1: face_acc_b<1>(sw, n2, xb, o, of); break;
-        case 2: face_acc_b<2>(sw, n2, xb, o, of); break;
-        default: face_acc_b<3>(sw, n2, xb, o, of); break;
-    }
-    const double dg = sw[0];
-    const size_t sa = (size_t)ca.x * B + ba, sb = (size_t)cb.x * B + bb;
-    if (MODE == 2) {
-        tmp[t] = ((double)f[sa] - of) / dg;
-        return;
-    }
-    double v = dg * (double)xa[ba] + of;
-    if (MODE == 1) v = (double)f[sa] - v;
-    y[sa] = (T)v;
-    y[sb] = (T)v;
+    face2_node<T, MODE>(x, y, f, cp, sten, n2, list, t, N, B, tmp);
 }
 
 // Combined face stencils: the element-wise partial stencils of both copies,
@@ -278,7 +174,8 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
 #define TS_DECL(Q, K)                                                                     \
     void launch_surr_q##Q##_k##K(const Level& L, int nt, const LevelOp& lo, int dtype,    \
                                  int center, int mode, const void* x, void* y,            \
-                                 const void* f, int colour, hipStream_t s);
+                                 const void* f, int colour, hipStream_t s,                \
+                                 const double* f2sten);
 TS_DECL(1, 2) TS_DECL(1, 4) TS_DECL(1, 8)
 TS_DECL(2, 2) TS_DECL(2, 4) TS_DECL(2, 8)
 TS_DECL(3, 2) TS_DECL(3, 4) TS_DECL(3, 8)
@@ -286,9 +183,9 @@ TS_DECL(4, 2) TS_DECL(4, 4) TS_DECL(4, 8)
 #undef TS_DECL
 
 void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                   const void* f, int colour, hipStream_t s) {
-    const Mesh& M = op->mesh->m;
-    const Level& L = const_cast<Mesh&>(M).level(lam);
+                   const void* f, int colour, hipStream_t s, bool fuse_face) {
+    Mesh& M = op->mesh->m;
+    const Level& L = M.level(lam);
     const LevelOp& lo = *op->lv.at(lam);
     const int nt = (int)M.nt, q = op->p.q, c = op->p.center;
     if (lo.n_ifem)  // selective surrogate: these macros keep IFEM rows
@@ -297,7 +194,9 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     if (lo.n_sur == 0) return;
     const int kpt = L.lds_kpt <= 2 ? 2 : L.lds_kpt <= 4 ? 4 : 8;
     TS_REQUIRE(L.lds_kpt <= 8, TS_EINVAL, "level too large for the surrogate volume kernel");
-#define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s)
+    // face rows fused into the launch (apply / residual); built on first use
+    const double* f2 = fuse_face && mode != 2 && L.n_f2 ? face_stencils(M, lam, s) : nullptr;
+#define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s, f2)
     switch (q * 16 + kpt) {
         case 18: TS_GO(1, 2); break;
         case 20: TS_GO(1, 4); break;
@@ -352,12 +251,12 @@ void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const voi
 // phase >= 0 computes the Gauss-Seidel values of that phase into tmp (face
 // fast path first, then the general nodes after it in tmp).
 void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                  const void* f, int phase, double* tmp, hipStream_t s) {
+                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face) {
     Mesh& M = op->mesh->m;
     const Level& L = M.level(lam);
     const double* sten = face_stencils(M, lam, s);
     const int* l2 = phase >= 0 ? L.f2_phase[phase].p : nullptr;
-    const int n2 = phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
+    const int n2 = skip_face ? 0 : phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
     double* tmp_r = tmp ? tmp + n2 : nullptr;

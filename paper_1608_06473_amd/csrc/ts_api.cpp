@@ -151,17 +151,22 @@ constexpr int kForkLevel = 6;
 // operator's side stream while the volume kernel runs on s.
 static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                     const void* f, hipStream_t s) {
+    const bool sur = uses_surrogate(op, lam);
+    // the face rows run inside the surrogate volume launch when it has work
+    const bool fuse = sur && op->lv.at(lam)->n_sur > 0;
     const bool fork = lam >= kForkLevel && op->side;
+    // stored interface rows are built (once) on s, before either stream reads them
+    face_stencils(op->mesh->m, lam, s);
     if (fork) {
         TS_HIP(hipEventRecord(op->ev_fork, s));
         TS_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, op->side);
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, op->side, fuse);
         TS_HIP(hipEventRecord(op->ev_join, op->side));
     } else {
-        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s);
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s, fuse);
     }
-    if (uses_surrogate(op, lam))
-        launch_volume(op, lam, dtype, mode, x, y, f, 0, s);
+    if (sur)
+        launch_volume(op, lam, dtype, mode, x, y, f, 0, s, fuse);
     else
         launch_ifem_volume(op, lam, dtype == TS_F16W ? TS_F32 : dtype, mode, x, y, f, 0, s);
     if (fork) TS_HIP(hipStreamWaitEvent(s, op->ev_join, 0));

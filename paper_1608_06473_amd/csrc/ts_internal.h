@@ -228,9 +228,9 @@ namespace ts {
 // vector dtype codes follow TS_F64 / TS_F32 / TS_F16W (the last two use
 // float vectors).
 void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                   const void* f, int colour, hipStream_t s);
+                   const void* f, int colour, hipStream_t s, bool fuse_face = false);
 void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                  const void* f, int phase, double* tmp, hipStream_t s);
+                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face = false);
 void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
                           void* u, hipStream_t s);
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,

@@ -14,6 +14,7 @@
 // arithmetic advances incrementally from plane to plane.
 #pragma once
 
+#include "ts_face.h"
 #include "ts_internal.h"
 
 namespace ts {
@@ -80,8 +81,9 @@ __device__ __forceinline__ T off_sum(const W s[NW], const T pm[7], const T p0[7]
 // that XCD's L2.
 // mlist (optional) maps the nt list positions to macro ids.
 __device__ __forceinline__ bool decode_block(int n_tiles, int nt, int& macro, int& tile,
-                                             const int* __restrict__ mlist = nullptr) {
-    const int b = blockIdx.x;
+                                             const int* __restrict__ mlist = nullptr,
+                                             int b = -1) {
+    if (b < 0) b = blockIdx.x;
     const int xcd = b & 7, loc = b >> 3;
     const int grp = loc / n_tiles;
     macro = grp * 8 + xcd;
@@ -282,10 +284,24 @@ __global__ __launch_bounds__(VOL_THREADS)
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
-                int N, int64_t B, int colour) {
+                int N, int64_t B, int colour, const int4* __restrict__ f2cp = nullptr,
+                const double* __restrict__ f2sten = nullptr, int n2 = 0) {
     constexpr int PF = TS_VOL_PF;
+    int bx = (int)blockIdx.x;
+    if (MODE != 2 && n2 > 0) {
+        // fused launch: per XCD, positions blockIdx / 8 in groups of three,
+        // two volume workgroups then one workgroup of 256 face rows (the
+        // face rows' gathers overlap the volume march on the same CUs)
+        const int xcd = bx & 7, loc = bx >> 3, grp = loc / 3, r3 = loc - 3 * grp;
+        if (r3 == 2) {
+            const int t = (grp * 8 + xcd) * VOL_THREADS + (int)threadIdx.x;
+            if (t < n2) face2_node<T, MODE>(x, y, f, f2cp, f2sten, n2, nullptr, t, N, B, nullptr);
+            return;
+        }
+        bx = ((grp * 2 + r3) << 3) | xcd;
+    }
     int macro, tile;
-    if (!decode_block(n_tiles, nt, macro, tile, mlist)) return;
+    if (!decode_block(n_tiles, nt, macro, tile, mlist, bx)) return;
     const int4 td = tiles[tile];
     const int k0 = td.x, j0 = td.y, j1 = td.z;
     const int tid = (int)threadIdx.x;

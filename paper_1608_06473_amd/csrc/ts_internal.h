@@ -156,6 +156,12 @@ struct Level {
 #ifndef TS_VOL_G
 #define TS_VOL_G 2
 #endif
+// minimum waves per SIMD the apply-mode surrogate volume kernel is compiled
+// for when q <= 2 and the staging width is 2 (levels up to 7): a budget of
+// 168 VGPRs at three waves, which those instantiations meet without spilling
+#ifndef TS_VOL_WAVES_EU
+#define TS_VOL_WAVES_EU 3
+#endif
 constexpr int VOL_R = TS_VOL_R;  // planes per volume tile
 constexpr int VOL_THREADS = 256;
 

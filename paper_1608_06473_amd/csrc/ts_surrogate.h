@@ -98,6 +98,7 @@ __device__ __forceinline__ bool decode_block(int n_tiles, int nt, int& macro, in
 // scaled coordinates).  W is the arithmetic type of the weights.
 template <int Q, typename W, int CENTER>
 struct SurrogateW {
+    static constexpr int kQ = Q;
     W d[NW][Q + 1];
     W invN;
     __device__ __forceinline__ void init_from(const float* __restrict__ cf,
@@ -191,6 +192,7 @@ struct SurrogateW {
 // products and sums stay in FP32.
 template <int Q>
 struct SurrogateHalfW {
+    static constexpr int kQ = Q;
     _Float16 d[NW][Q + 1];
     float invN;
     __device__ __forceinline__ void init_from(const float* __restrict__ cf,
@@ -281,6 +283,7 @@ __device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g0, in
 // weight arithmetic type (float for the FP16 provider's products).
 template <class WP, typename T, typename W, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS)
+__attribute__((amdgpu_waves_per_eu(MODE == 0 && WP::kQ <= 2 && KPT <= 2 ? TS_VOL_WAVES_EU : 1)))
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,

@@ -156,9 +156,10 @@ struct Level {
 #ifndef TS_VOL_G
 #define TS_VOL_G 2
 #endif
-// minimum waves per SIMD the apply-mode surrogate volume kernel is compiled
-// for when q <= 2 and the staging width is 2 (levels up to 7): a budget of
-// 168 VGPRs at three waves, which those instantiations meet without spilling
+// minimum waves per SIMD the apply- and residual-mode surrogate volume
+// kernels are compiled for when q <= 2 and the staging width is 2 (levels up
+// to 7): a budget of 168 VGPRs at three waves, which those instantiations meet
+// without spilling (FP32 ones use under 100 anyway)
 #ifndef TS_VOL_WAVES_EU
 #define TS_VOL_WAVES_EU 3
 #endif

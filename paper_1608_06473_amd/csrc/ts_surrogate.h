@@ -283,13 +283,15 @@ __device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g0, in
 // weight arithmetic type (float for the FP16 provider's products).
 template <class WP, typename T, typename W, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS)
-__attribute__((amdgpu_waves_per_eu(MODE == 0 && WP::kQ <= 2 && KPT <= 2 ? TS_VOL_WAVES_EU : 1)))
+__attribute__((amdgpu_waves_per_eu(MODE != 2 && WP::kQ <= 2 && KPT <= 2 ? TS_VOL_WAVES_EU : 1)))
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
                 int N, int64_t B, int colour, const int4* __restrict__ f2cp = nullptr,
                 const double* __restrict__ f2sten = nullptr, int n2 = 0) {
-    constexpr int PF = TS_VOL_PF;
+    // the residual's f ring needs registers: shorter staging prefetch there
+    // when the kernel is compiled for three waves
+    constexpr int PF = MODE == 1 && WP::kQ <= 2 && KPT <= 2 ? 2 : TS_VOL_PF;
     int bx = (int)blockIdx.x;
     if (MODE != 2 && n2 > 0) {
         // fused launch: per XCD, positions blockIdx / 8 in groups of three,

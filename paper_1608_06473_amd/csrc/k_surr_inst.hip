@@ -35,11 +35,11 @@ static void run(const Level& L, int nt, const int* ml, const float* cf, const do
         gf = dim3((unsigned)(groups * 3 * 8));
     }
     if (mode == 0)
-        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<gf, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.N, L.B, colour, L.f2_cp.p, f2sten, n2);
+        k_surr_lds<WP, T, W, 0, VOL_R, TS_KPT><<<gf, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.stage_tbl.p, L.N, L.B, colour, L.f2_cp.p, f2sten, n2);
     else if (mode == 1)
-        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<gf, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.N, L.B, colour, L.f2_cp.p, f2sten, n2);
+        k_surr_lds<WP, T, W, 1, VOL_R, TS_KPT><<<gf, blk, 0, s>>>(xp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.ap_lanes.p, L.stage_tbl.p, L.N, L.B, colour, L.f2_cp.p, f2sten, n2);
     else
-        k_surr_lds<WP, T, W, 2, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(yp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.gs_lanes.p, L.N, L.B, colour);
+        k_surr_lds<WP, T, W, 2, VOL_R, TS_KPT><<<grid, blk, 0, s>>>(yp, yp, fp, cf, cd, L.lds_tiles.p, L.n_lds_tiles, nt, ml, L.gs_lanes.p, L.stage_tbl.p, L.N, L.B, colour);
 }
 
 // dtype TS_F64: FP64 vectors and weights; TS_F32: FP32; TS_F16W: FP32 vectors

@@ -115,6 +115,8 @@ struct Level {
     int lds_kpt = 0;              // staged values per thread and plane
     DBuf<unsigned> gs_lanes;      // per tile and lane: i | j << 16 (GS order)
     DBuf<unsigned> ap_lanes;      // per tile and lane: i | j << 16 (apply order)
+    DBuf<int> stage_tbl;          // per tile and staged plane k0-1+st (st = 0..R+1):
+                                  // first block element of rows j0-1 .. j1 (0 if none)
     DBuf<double> xyz;             // blended coordinates of every slot (x, y, z),
                                   // built on the first element-wise volume pass
     // fast path for free nodes of interior faces (exactly two copies): node

@@ -269,11 +269,10 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
 }
 
 // Staging loads of one plane range: KPT consecutive entries per lane from
-// element g0 on; entries past the range are never used by a live step (and
+// element g on; entries past the range are never used by a live step (and
 // read 0 past the block's end).
 template <typename T, int KPT>
-__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g0, int cnt, T r[KPT]) {
-    const int g = cnt > 0 ? g0 : 0;
+__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g, T r[KPT]) {
 #pragma unroll
     for (int s = 0; s < KPT; s++)
         r[s] = bload<T>(rx, (g + (int)threadIdx.x + s * VOL_THREADS) * (int)sizeof(T));
@@ -287,7 +286,8 @@ __attribute__((amdgpu_waves_per_eu(MODE != 2 && WP::kQ <= 2 && KPT <= 2 ? TS_VOL
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
                 const double* __restrict__ coef_d, const int4* __restrict__ tiles, int n_tiles,
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
-                int N, int64_t B, int colour, const int4* __restrict__ f2cp = nullptr,
+                const int* __restrict__ stage, int N, int64_t B, int colour,
+                const int4* __restrict__ f2cp = nullptr,
                 const double* __restrict__ f2sten = nullptr, int n2 = 0) {
     // the residual's f ring needs registers: shorter staging prefetch there
     // when the kernel is compiled for three waves
@@ -338,27 +338,33 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     const __amdgpu_buffer_rsrc_t ry = block_rsrc(y + base, bbytes);
     const __amdgpu_buffer_rsrc_t rf = block_rsrc(f ? f + base : x + base, bbytes);
 
-    // Incremental state.  Plane p has side A = N + 1 - p and po(p) points
-    // before it; po(p + 1) = po(p) + A (A + 1) / 2.  The staged range of
-    // plane p starts at row j0 - 1 (jb): g0 = po + jb A - jb (jb - 1) / 2.
+    // Staged range of plane p = k0 - 1 + st: rows jb = j0 - 1 .. min(j1, N - p)
+    // from element plane_off(p) + row_off(jb, p) of the block.  FP32
+    // kernels read it from the per-level table stage[tile][st]; the FP64
+    // kernels, at their register limit, advance it incrementally instead
+    // (plane p has side A = N + 1 - p, and plane_off grows by A (A + 1) / 2).
+    const int* __restrict__ sgt = stage + (size_t)tile * (R + 2);
     const int jb = j0 - 1, jtri = jb * (jb - 1) / 2;
+    int po_pf = (int)plane_off(N, k0 - 1);
+    auto sg = [&](int st) {
+        if constexpr (sizeof(T) == 4) {
+            return sgt[st];
+        } else {
+            const int p = k0 - 1 + st;
+            const int A = N + 1 - p;
+            const int jl = min(j1, N - p);
+            const int g = (p <= N && jl >= jb) ? po_pf + jb * A - jtri : 0;
+            po_pf += A * (A + 1) / 2;
+            return g;
+        }
+    };
     // lane: LDS index c of (i, j) = sum_{jb <= r < j} (A - r) + i; it drops by
     // nb = j - jb from one plane to the next; qa = A - j drops by 1
     const int nb = j - jb;
     const int srow = (jb + j - 1) * nb / 2;
-    // global index of (i, j, k) advances by T(N + 1 - k) - j
-    int po_pf = (int)plane_off(N, k0 - 1);
     T pf[PF][KPT];
 #pragma unroll
-    for (int d = 0; d < PF; d++) {
-        const int p = k0 - 1 + d;
-        const int A = N + 1 - p;
-        const int jl = min(j1, N - p);
-        const int nr = jl - jb + 1;
-        const int cnt = (p <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
-        stage_load<T, KPT>(rx, po_pf + jb * A - jtri, cnt, pf[d]);
-        po_pf += A * (A + 1) / 2;
-    }
+    for (int d = 0; d < PF; d++) stage_load<T, KPT>(rx, sg(d), pf[d]);
     int A0 = N + 2 - k0;                 // side of plane k0 - 1
     int c = nb * A0 - srow + i;          // LDS index in plane k0 - 1
     int qa = A0 - j;
@@ -396,19 +402,10 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     for (int g0 = 0; g0 < R + 2; g0 += G) {
 #pragma unroll
     for (int st = g0; st < g0 + G && st < R + 2; st++) {
-        const int p = k0 - 1 + st;
         T* bb = buf[st % (2 * G)];
 #pragma unroll
         for (int s2 = 0; s2 < KPT; s2++) bb[tid + s2 * VOL_THREADS] = pf[st % PF][s2];
-        if (st + PF <= R + 1) {
-            const int pq = p + PF;
-            const int A = N + 1 - pq;
-            const int jl = min(j1, N - pq);
-            const int nr = jl - jb + 1;
-            const int cnt = (pq <= N && nr > 0) ? nr * A - (jb + jl) * nr / 2 : 0;
-            stage_load<T, KPT>(rx, po_pf + jb * A - jtri, cnt, pf[st % PF]);
-            po_pf += A * (A + 1) / 2;
-        }
+        if (st + PF <= R + 1) stage_load<T, KPT>(rx, sg(st + PF), pf[st % PF]);
     }
     __syncthreads();
 #pragma unroll

@@ -369,6 +369,22 @@ Level& Mesh::level(int lam) {
         L->ap_lanes.upload(am);
         L->gs_lanes.upload(gm);
     }
+    // staged plane ranges of every tile: plane p = k0 - 1 + st holds rows
+    // jb = j0 - 1 .. min(j1, N - p), starting at plane_off(p) + row_off(jb, p)
+    {
+        std::vector<int> sg((size_t)lt.size() * (VOL_R + 2), 0);
+        for (size_t t = 0; t < lt.size(); t++) {
+            const int4 d = lt[t];
+            const int jb = d.y - 1;
+            for (int st = 0; st < VOL_R + 2; st++) {
+                const int p = d.x - 1 + st;
+                const int jl = std::min(d.z, N - p);
+                if (p <= N && jl >= jb)
+                    sg[t * (VOL_R + 2) + st] = (int)(plane_off(N, p) + row_off(N, jb, p));
+            }
+        }
+        L->stage_tbl.upload(sg);
+    }
     // all-slot tiles: every plane k = 0..N in chunks of 256 slots
     std::vector<int2> st;
     for (int k = 0; k <= N; k++) {

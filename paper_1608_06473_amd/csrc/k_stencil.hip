@@ -130,6 +130,12 @@ const double* face_stencils(Mesh& M, int lam, hipStream_t s) {
                                                               M.d_topo.p, L.N, L.f2_sten.p);
         TS_HIP(hipGetLastError());
     }
+    if (!L.f2g_sten.p && L.n_f2) {
+        L.f2g_sten.alloc((size_t)NW * L.n_f2);
+        k_face2_stencils<<<(L.n_f2 + 127) / 128, 128, 0, s>>>(L.f2g_cp.p, L.n_f2, M.d_geom.p,
+                                                              M.d_topo.p, L.N, L.f2g_sten.p);
+        TS_HIP(hipGetLastError());
+    }
     if (!L.rest_sten.p && L.n_rc) {
         L.rest_sten.alloc((size_t)NW * L.n_rc);
         k_copy_stencils<<<(L.n_rc + 127) / 128, 128, 0, s>>>(L.rc_cp.p, L.n_rc, M.d_geom.p, L.N,
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
                                                        int64_t B) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const int q = list[t];
+    const int q = list ? list[t] : t;
     const T v = (T)tmp[t];
 #pragma unroll
     for (int r = 0; r < 2; r++) {
@@ -254,15 +260,19 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
                   const void* f, int phase, double* tmp, hipStream_t s, bool skip_face) {
     Mesh& M = op->mesh->m;
     const Level& L = M.level(lam);
-    const double* sten = face_stencils(M, lam, s);
-    const int* l2 = phase >= 0 ? L.f2_phase[phase].p : nullptr;
+    face_stencils(M, lam, s);
+    // apply / residual: canonical order; Gauss-Seidel phase: its contiguous
+    // range of the phase-grouped copy
+    const int go = phase >= 0 ? L.f2g_off[phase] : 0;
+    const int4* cp2 = phase >= 0 ? L.f2g_cp.p + go : L.f2_cp.p;
+    const double* sten = phase >= 0 ? L.f2g_sten.p + go : L.f2_sten.p;
     const int n2 = skip_face ? 0 : phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
     double* tmp_r = tmp ? tmp + n2 : nullptr;
 #define TS_F2(T_, M_)                                                                         \
     k_face2<T_, M_><<<(n2 + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,       \
-                                                     L.f2_cp.p, sten, L.n_f2, l2, n2, L.N,    \
+                                                     cp2, sten, L.n_f2, nullptr, n2, L.N,     \
                                                      L.B, tmp)
 #define TS_IF(T_, M_)                                                                         \
     k_iface<T_, M_><<<(nr + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,       \
@@ -302,9 +312,9 @@ void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const 
     const int n2 = L.n_f2_phase[phase], nr = L.n_rest_phase[phase];
     if (n2) {
         if (dtype == TS_F64)
-            k_face2_scatter<double><<<(n2 + 255) / 256, 256, 0, s>>>((double*)u, tmp, L.f2_cp.p, L.n_f2, L.f2_phase[phase].p, n2, L.N, L.B);
+            k_face2_scatter<double><<<(n2 + 255) / 256, 256, 0, s>>>((double*)u, tmp, L.f2g_cp.p + L.f2g_off[phase], L.n_f2, nullptr, n2, L.N, L.B);
         else
-            k_face2_scatter<float><<<(n2 + 255) / 256, 256, 0, s>>>((float*)u, tmp, L.f2_cp.p, L.n_f2, L.f2_phase[phase].p, n2, L.N, L.B);
+            k_face2_scatter<float><<<(n2 + 255) / 256, 256, 0, s>>>((float*)u, tmp, L.f2g_cp.p + L.f2g_off[phase], L.n_f2, nullptr, n2, L.N, L.B);
     }
     if (nr) {
         if (dtype == TS_F64)

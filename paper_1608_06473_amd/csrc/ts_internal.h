@@ -139,10 +139,15 @@ struct Level {
     // block slots of every copy of every Dirichlet node (zero rows)
     DBuf<int64_t> dir_slots;
     int64_t n_dir_slots = 0;
-    // per GS phase: positions in the face fast path / in the general lists
-    DBuf<int> f2_phase[N_IF_PHASES];
+    // Gauss-Seidel copy of the face fast path, grouped by phase: copies
+    // [2][n_f2] and combined rows [15][n_f2]; phase p is the range
+    // f2g_off[p] .. f2g_off[p] + n_f2_phase[p]
+    DBuf<int4> f2g_cp;
+    DBuf<double> f2g_sten;
+    int f2g_off[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
     int n_f2_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
-    DBuf<int> rest_phase[N_IF_PHASES];  // node ids
+    // per GS phase: node ids of the general lists
+    DBuf<int> rest_phase[N_IF_PHASES];
     int n_rest_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
 };
 

@@ -261,17 +261,28 @@ Level& Mesh::level(int lam) {
         L->f2_cp.upload(c01);
         L->n_rest = (int)rest.size();
         L->rest.upload(rest);
+        // Gauss-Seidel copy of the face fast path: the same nodes grouped by
+        // phase, so that phase p is the contiguous range f2g_off[p] ..
+        std::vector<int4> g0, g1;
         for (int p = 0; p < N_IF_PHASES; p++) {
-            std::vector<int> a, b;
+            std::vector<int> b;
+            L->f2g_off[p] = (int)g0.size();
+            int n2p = 0;
             for (int n : lists[p]) {
-                if (f2pos[n] >= 0) a.push_back(f2pos[n]);
-                else b.push_back(n);
+                if (f2pos[n] >= 0) {
+                    g0.push_back(c0[f2pos[n]]);
+                    g1.push_back(c1[f2pos[n]]);
+                    n2p++;
+                } else {
+                    b.push_back(n);
+                }
             }
-            L->f2_phase[p].upload(a);
-            L->n_f2_phase[p] = (int)a.size();
+            L->n_f2_phase[p] = n2p;
             L->rest_phase[p].upload(b);
             L->n_rest_phase[p] = (int)b.size();
         }
+        g0.insert(g0.end(), g1.begin(), g1.end());
+        L->f2g_cp.upload(g0);
     }
 
     // LDS-staged tiles: whole rows of plane k0's interior up to 256

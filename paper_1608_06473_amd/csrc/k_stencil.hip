@@ -12,25 +12,26 @@
 namespace ts {
 
 // Lower primitives -------------------------------------------------------------
-// General path: one thread per listed free face/edge/vertex node, summing
-// over the node's copies the stored element-wise partial stencil of each
-// adjacent macro.  MODE 0: y = L x; 1: y = f - L x, written to every copy;
-// 2: Gauss-Seidel value (f - off) / diag into tmp[t].
+// General path: one wavefront per listed free face/edge/vertex node (four
+// nodes per workgroup).  The lanes take the node's copies (the stored
+// element-wise partial stencil of each adjacent macro), the partial sums are
+// reduced across the wavefront in a fixed tree order, and the lanes write the
+// copies.  MODE 0: y = L x; 1: y = f - L x, written to every copy; 2:
+// Gauss-Seidel value (f - off) / diag into tmp[t].
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_iface(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
     const int* __restrict__ off, const int4* __restrict__ cp, const int* __restrict__ rc_base,
     const double* __restrict__ sten, int n_rc, const int* __restrict__ list, int n, int N,
     int64_t B, double* __restrict__ tmp) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
+    const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    if (t >= n) return;  // whole wavefront
     const int node = list[t];
     const int c0 = off[node], c1 = off[node + 1];
     const int rb = rc_base[node] - c0;
-    const int4 q0 = cp[c0];
-    const size_t s0 = (size_t)q0.x * B + bidx(N, q0.y, q0.z, q0.w);
     double dg = 0.0, of = 0.0;
-    for (int c = c0; c < c1; c++) {
+    for (int c = c0 + lane; c < c1; c += 64) {
         const int4 q = cp[c];
         const double* sw = sten + rb + c;
         const T* xm = x + (size_t)q.x * B;
@@ -42,13 +43,20 @@ __global__ __launch_bounds__(256) void k_iface(
             if (inside(N, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w)))
                 of += sw[(size_t)w * n_rc] * (double)xm[o[w]];
     }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        dg += __shfl_xor(dg, m, 64);
+        of += __shfl_xor(of, m, 64);
+    }
+    const int4 q0 = cp[c0];
+    const size_t s0 = (size_t)q0.x * B + bidx(N, q0.y, q0.z, q0.w);
     if (MODE == 2) {
-        tmp[t] = ((double)f[s0] - of) / dg;
+        if (lane == 0) tmp[t] = ((double)f[s0] - of) / dg;
         return;
     }
     double v = dg * (double)x[s0] + of;
     if (MODE == 1) v = (double)f[s0] - v;
-    for (int c = c0; c < c1; c++) {
+    for (int c = c0 + lane; c < c1; c += 64) {
         const int4 q = cp[c];
         y[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = (T)v;
     }
@@ -275,7 +283,7 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
                                                      cp2, sten, L.n_f2, nullptr, n2, L.N,     \
                                                      L.B, tmp)
 #define TS_IF(T_, M_)                                                                         \
-    k_iface<T_, M_><<<(nr + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,       \
+    k_iface<T_, M_><<<(nr + 3) / 4, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,           \
                                                      L.if_off.p, L.if_copy.p, L.rc_base.p,    \
                                                      L.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
                                                      tmp_r)

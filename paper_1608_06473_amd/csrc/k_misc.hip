@@ -12,10 +12,12 @@ namespace ts {
 
 // ---------------------------------------------------------------- helpers
 
-// slot (position r in plane k) -> (i, j): row j has A - j slots, A = N+1-k
+// slot (position r in plane k) -> (i, j): row j has A - j slots, A = N+1-k.
+// The FP32 estimate is exact enough (operands below 2^24) for the integer
+// fix-up to need at most one step.
 __device__ __forceinline__ void plane_pos_to_ij(int r, int A, int& i, int& j) {
-    const double a = 2.0 * A + 1.0;
-    int J = (int)((a - sqrt(a * a - 8.0 * r)) * 0.5);
+    const float a = 2.0f * (float)A + 1.0f;
+    int J = (int)((a - sqrtf(a * a - 8.0f * (float)r)) * 0.5f);
     if (J < 0) J = 0;
     while (J > 0 && J * (2 * A - J + 1) / 2 > r) J--;
     while ((J + 1) * (2 * A - J) / 2 <= r) J++;
@@ -79,34 +81,69 @@ __device__ __forceinline__ int node_mult(const MacroTopo& T, int N, int i, int j
 
 // coarse lower-primitive nodes: sum over the node's copies of the fine
 // midpoints in that macro, each divided by the number of macros that hold it
+// sum over the 14 neighbours w of coarse copy q of the fine values at the
+// midpoints 2q + w, each shared by the fine node's copies (the restriction
+// R = P^T accumulated once over all copies)
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_iface(
-    const T* __restrict__ rf, T* __restrict__ rc, const int* __restrict__ off,
-    const int4* __restrict__ cp, const unsigned char* __restrict__ flag, int n,
+__device__ __forceinline__ double restrict_copy(const T* __restrict__ rf, int4 q,
+                                                const MacroTopo& TP, int Nc, int64_t Bf) {
+    const int Nf = 2 * Nc;
+    const T* fm = rf + (size_t)q.x * Bf;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 1; w < NW; w++) {
+        if (!inside(Nc, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w))) continue;
+        const int a = 2 * q.y + dir_i(w), b = 2 * q.z + dir_j(w), cc = 2 * q.w + dir_k(w);
+        v += 0.5 * (double)fm[bidx(Nf, a, b, cc)] / (double)node_mult(TP, Nf, a, b, cc);
+    }
+    return v;
+}
+
+// coarse face nodes with two copies: one thread per node
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_face2(
+    const T* __restrict__ rf, T* __restrict__ rc, const int4* __restrict__ cp, int n2,
     const MacroTopo* __restrict__ topo, int Nc, int64_t Bf, int64_t Bc) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n2) return;
+    const int4 qa = cp[t], qb = cp[(size_t)n2 + t];
+    double v = (double)rf[(size_t)qa.x * Bf + bidx(2 * Nc, 2 * qa.y, 2 * qa.z, 2 * qa.w)];
+    v += restrict_copy(rf, qa, topo[qa.x], Nc, Bf);
+    v += restrict_copy(rf, qb, topo[qb.x], Nc, Bf);
+    rc[(size_t)qa.x * Bc + bidx(Nc, qa.y, qa.z, qa.w)] = (T)v;
+    rc[(size_t)qb.x * Bc + bidx(Nc, qb.y, qb.z, qb.w)] = (T)v;
+}
+
+// other free coarse interface nodes (edges, vertices): one wavefront per
+// node, copies across lanes, fixed-order reduction
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_rest(
+    const T* __restrict__ rf, T* __restrict__ rc, const int* __restrict__ off,
+    const int4* __restrict__ cp, const int* __restrict__ list, int n,
+    const MacroTopo* __restrict__ topo, int Nc, int64_t Bf, int64_t Bc) {
+    const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
     if (t >= n) return;
-    const int c0 = off[t], c1 = off[t + 1];
+    const int node = list[t];
+    const int c0 = off[node], c1 = off[node + 1];
     double v = 0.0;
-    if (!(flag[t] & 1)) {
-        const int Nf = 2 * Nc;
-        const int4 q0 = cp[c0];
-        v = (double)rf[(size_t)q0.x * Bf + bidx(Nf, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
-        for (int c = c0; c < c1; c++) {
-            const int4 q = cp[c];
-            const MacroTopo& TP = topo[q.x];
-            const T* fm = rf + (size_t)q.x * Bf;
-            for (int w = 1; w < NW; w++) {
-                if (!inside(Nc, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w))) continue;
-                const int a = 2 * q.y + dir_i(w), b = 2 * q.z + dir_j(w), cc = 2 * q.w + dir_k(w);
-                v += 0.5 * (double)fm[bidx(Nf, a, b, cc)] / (double)node_mult(TP, Nf, a, b, cc);
-            }
-        }
-    }
-    for (int c = c0; c < c1; c++) {
+    for (int c = c0 + lane; c < c1; c += 64) v += restrict_copy(rf, cp[c], topo[cp[c].x], Nc, Bf);
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    const int4 q0 = cp[c0];
+    v += (double)rf[(size_t)q0.x * Bf + bidx(2 * Nc, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
+    for (int c = c0 + lane; c < c1; c += 64) {
         const int4 q = cp[c];
         rc[(size_t)q.x * Bc + bidx(Nc, q.y, q.z, q.w)] = (T)v;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_slots_misc(T* __restrict__ y,
+                                                         const int64_t* __restrict__ slots,
+                                                         int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[slots[t]] = (T)0;
 }
 
 // u_f += P u_c over every fine slot: even nodes copy the coarse node, odd
@@ -145,14 +182,23 @@ void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* 
     const Level& Lf = MM.level(lam_f);
     const Level& Lc = MM.level(lam_f - 1);
     const dim3 g1(Lc.n_slot_tiles, (unsigned)M.nt), b1(256);
-    const dim3 g2((unsigned)((Lc.n_if + 255) / 256)), b2(256);
+    const unsigned g2 = (unsigned)((Lc.n_f2 + 255) / 256), g3 = (unsigned)((Lc.n_rest + 3) / 4);
+    const unsigned g4 = (unsigned)((Lc.n_dir_slots + 255) / 256);
+#define TS_R(T_)                                                                                  \
+    k_restrict_volume<T_><<<g1, b1, 0, s>>>((const T_*)rf, (T_*)rc, Lc.slot_tiles.p, Lc.N, Lf.B,  \
+                                            Lc.B);                                                \
+    if (g2) k_restrict_face2<T_><<<g2, 256, 0, s>>>((const T_*)rf, (T_*)rc, Lc.f2_cp.p, Lc.n_f2,  \
+                                                    M.d_topo.p, Lc.N, Lf.B, Lc.B);                \
+    if (g3) k_restrict_rest<T_><<<g3, 256, 0, s>>>((const T_*)rf, (T_*)rc, Lc.if_off.p,           \
+                                                   Lc.if_copy.p, Lc.rest.p, Lc.n_rest,            \
+                                                   M.d_topo.p, Lc.N, Lf.B, Lc.B);                 \
+    if (g4) k_zero_slots_misc<T_><<<g4, 256, 0, s>>>((T_*)rc, Lc.dir_slots.p, Lc.n_dir_slots)
     if (dtype == TS_F64) {
-        k_restrict_volume<double><<<g1, b1, 0, s>>>((const double*)rf, (double*)rc, Lc.slot_tiles.p, Lc.N, Lf.B, Lc.B);
-        k_restrict_iface<double><<<g2, b2, 0, s>>>((const double*)rf, (double*)rc, Lc.if_off.p, Lc.if_copy.p, Lc.if_flag.p, (int)Lc.n_if, M.d_topo.p, Lc.N, Lf.B, Lc.B);
+        TS_R(double);
     } else {
-        k_restrict_volume<float><<<g1, b1, 0, s>>>((const float*)rf, (float*)rc, Lc.slot_tiles.p, Lc.N, Lf.B, Lc.B);
-        k_restrict_iface<float><<<g2, b2, 0, s>>>((const float*)rf, (float*)rc, Lc.if_off.p, Lc.if_copy.p, Lc.if_flag.p, (int)Lc.n_if, M.d_topo.p, Lc.N, Lf.B, Lc.B);
+        TS_R(float);
     }
+#undef TS_R
     TS_HIP(hipGetLastError());
 }
 
@@ -235,21 +281,28 @@ __device__ __forceinline__ double block_sum(double v) {
     return sh[0];
 }
 
-// one workgroup per (plane k = 1 .. N-3, macro): the interior rows of the
-// plane are contiguous runs of the block layout
+// one workgroup per (volume tile, macro): each lane sums the squares of its
+// column's interior nodes in the tile's slab (the columns of the volume
+// kernel, in its apply order)
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x, int N, int64_t B,
-                                                     double* __restrict__ partial) {
-    const int k = 1 + (int)blockIdx.x;
-    const int macro = blockIdx.y;
-    const T* xm = x + (size_t)macro * B + plane_off(N, k);
+__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x,
+                                                     const int4* __restrict__ tiles,
+                                                     const unsigned* __restrict__ lanes, int N,
+                                                     int64_t B, double* __restrict__ partial) {
+    const int tile = blockIdx.x, macro = blockIdx.y;
+    const int k0 = tiles[tile].x;
+    const unsigned e = lanes[(size_t)tile * 256 + threadIdx.x];
     double v = 0.0;
-    for (int j = 1; j <= N - 2 - k; j++) {
-        const int64_t r0 = row_off(N, j, k);
-        const int len = N - 1 - j - k;  // i = 1 .. len
-        for (int i = 1 + (int)threadIdx.x; i <= len; i += 256) {
-            const double a = (double)xm[r0 + i];
+    if (e != 0xFFFFFFFFu) {
+        const int i = (int)(e & 0xFFFFu), j = (int)(e >> 16);
+        const int nlive = min(N - 1 - i - j, k0 + VOL_R - 1) - k0 + 1;
+        const T* xm = x + (size_t)macro * B;
+        int idx = (int)bidx(N, i, j, k0);
+        for (int r = 0; r < nlive; r++) {
+            const double a = (double)xm[idx];
             v += a * a;
+            const int Ak = N + 1 - (k0 + r);
+            idx += Ak * (Ak + 1) / 2 - j;
         }
     }
     const double s = block_sum(v);
@@ -286,8 +339,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 static int64_t volume_partials(const Mesh& M, int lam) {
-    const int N = 1 << lam;
-    return (int64_t)(N > 3 ? N - 3 : 0) * M.nt;
+    const Level& L = const_cast<Mesh&>(M).level(lam);
+    return (int64_t)L.n_lds_tiles * M.nt;
 }
 
 int64_t norm_partial_count(const Mesh& M, int lam) {
@@ -303,11 +356,11 @@ void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double*
     const int64_t n1 = volume_partials(M, lam);
     const int n2 = (L.n_if_free + 255) / 256;
     if (n1) {
-        const dim3 g1((unsigned)(L.N - 3), (unsigned)M.nt);
+        const dim3 g1((unsigned)L.n_lds_tiles, (unsigned)M.nt);
         if (dtype == TS_F64)
-            k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.N, L.B, partial);
+            k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
         else
-            k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.N, L.B, partial);
+            k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
     }
     if (n2) {
         if (dtype == TS_F64)

@@ -6,6 +6,8 @@
 // coarsest-level dense inverse (Gauss-Jordan) with its solve.
 #include <math.h>
 
+#include <algorithm>
+
 #include "ts_internal.h"
 
 namespace ts {
@@ -762,6 +764,131 @@ __global__ __launch_bounds__(256) void k_gj_update(double* A, const double* __re
 void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s) {
     k_gj_pivot<<<1, 256, 0, s>>>(A, col, n, k);
     k_gj_update<<<dim3((n + 255) / 256, n), 256, 0, s>>>(A, col, n, k);
+}
+
+// Blocked in-place Gauss-Jordan inversion of the SPD coarse matrix (row-major
+// n x n), pivot blocks K = k0 .. k0+b-1 of at most GJB rows in order:
+//   D = A[K,K]^-1;  P = D A[K,:];  A[i,j] -= A[i,K] P[:,j] (i, j outside K);
+//   A[i,K] = -A[i,K] D (i outside K);  A[K,j] = P[:,j] (j outside K);  A[K,K] = D.
+constexpr int GJB = 64;
+
+// D = A[K,K]^-1 by unblocked Gauss-Jordan in LDS (one workgroup)
+__global__ __launch_bounds__(256) void k_bgj_diag(const double* __restrict__ A, int n, int k0,
+                                                  int b, double* __restrict__ D) {
+    __shared__ double M[GJB][GJB + 1];
+    __shared__ double col[GJB];
+    for (int e = threadIdx.x; e < b * b; e += 256) M[e / b][e % b] = A[(size_t)(k0 + e / b) * n + k0 + e % b];
+    __syncthreads();
+    for (int k = 0; k < b; k++) {
+        const double piv = M[k][k];
+        if (threadIdx.x < b) col[threadIdx.x] = M[threadIdx.x][k];
+        __syncthreads();
+        if (threadIdx.x < b) {
+            const int j = threadIdx.x;
+            M[k][j] = (j == k) ? 1.0 / piv : M[k][j] / piv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < b * b; e += 256) {
+            const int i = e / b, j = e % b;
+            if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - col[i] * M[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < b * b; e += 256) D[e] = M[e / b][e % b];
+}
+
+// P[r][j] = sum_s D[r][s] A[k0+s][j] for every column j (b x n)
+__global__ __launch_bounds__(256) void k_bgj_panel(const double* __restrict__ A, int n, int k0,
+                                                   int b, const double* __restrict__ D,
+                                                   double* __restrict__ P) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= n) return;
+    double v = 0.0;
+    for (int q = 0; q < b; q++) v += D[r * b + q] * A[(size_t)(k0 + q) * n + j];
+    P[(size_t)r * n + j] = v;
+}
+
+// A[i][j] -= sum_s A[i][k0+s] P[s][j] for i, j outside the pivot block:
+// 64 x 64 output tiles, 4 x 4 per thread, operands staged in LDS
+__global__ __launch_bounds__(256) void k_bgj_update(double* __restrict__ A, int n, int k0, int b,
+                                                    const double* __restrict__ P) {
+    __shared__ double Ls[GJB][GJB + 1];  // A[i0 + r][k0 + s]
+    __shared__ double Ps[GJB][GJB + 1];  // P[s][j0 + c]
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    for (int e = threadIdx.x; e < 64 * GJB; e += 256) {
+        const int r = e / GJB, q = e % GJB;
+        Ls[r][q] = (i0 + r < n && q < b) ? A[(size_t)(i0 + r) * n + k0 + q] : 0.0;
+        const int c = e % 64, q2 = e / 64;
+        Ps[q2][c] = (j0 + c < n && q2 < b) ? P[(size_t)q2 * n + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+    double acc[4][4] = {};
+    for (int q = 0; q < b; q++) {
+        double a[4], p[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            a[u] = Ls[tr + u][q];
+            p[u] = Ps[q][tc + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[u][v] += a[u] * p[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int i = i0 + tr + u;
+        if (i >= n || (i >= k0 && i < k0 + b)) continue;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int j = j0 + tc + v;
+            if (j >= n || (j >= k0 && j < k0 + b)) continue;
+            A[(size_t)i * n + j] -= acc[u][v];
+        }
+    }
+}
+
+// A[i][K] = -A[i][K] D for rows outside K; then the pivot rows and block
+__global__ __launch_bounds__(256) void k_bgj_cols(double* __restrict__ A, int n, int k0, int b,
+                                                  const double* __restrict__ D) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || (i >= k0 && i < k0 + b)) return;
+    double row[GJB];
+#pragma unroll
+    for (int q = 0; q < GJB; q++) row[q] = q < b ? A[(size_t)i * n + k0 + q] : 0.0;
+    for (int c = 0; c < b; c++) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < GJB; q++)
+            if (q < b) v += row[q] * D[q * b + c];
+        A[(size_t)i * n + k0 + c] = -v;
+    }
+}
+__global__ __launch_bounds__(256) void k_bgj_rows(double* __restrict__ A, int n, int k0, int b,
+                                                  const double* __restrict__ P,
+                                                  const double* __restrict__ D) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= n) return;
+    A[(size_t)(k0 + r) * n + j] = (j >= k0 && j < k0 + b) ? D[r * b + (j - k0)] : P[(size_t)r * n + j];
+}
+
+// work: at least GJB * (n + GJB) doubles
+void launch_gj_blocked(double* A, int n, double* work, hipStream_t s) {
+    double* D = work;
+    double* P = work + GJB * GJB;
+    const unsigned gt = (unsigned)((n + 63) / 64), gc = (unsigned)((n + 255) / 256);
+    for (int k0 = 0; k0 < n; k0 += GJB) {
+        const int b = std::min(GJB, n - k0);
+        k_bgj_diag<<<1, 256, 0, s>>>(A, n, k0, b, D);
+        k_bgj_panel<<<dim3(gc, b), 256, 0, s>>>(A, n, k0, b, D, P);
+        k_bgj_update<<<dim3(gt, gt), 256, 0, s>>>(A, n, k0, b, P);
+        k_bgj_cols<<<gc, 256, 0, s>>>(A, n, k0, b, D);
+        k_bgj_rows<<<dim3(gc, b), 256, 0, s>>>(A, n, k0, b, P, D);
+    }
+    TS_HIP(hipGetLastError());
 }
 
 // u = Ainv f on the coarsest level: gather f at the first copy of each free

@@ -290,12 +290,12 @@ static void coarse_setup(ts_solver* sv, hipStream_t s) {
     d_sf.upload(slot_free);
     sv->c_off.upload(off);
     sv->c_slot.upload(slot);
-    DBuf<double> A, col;
+    DBuf<double> A, work;
     A.alloc((size_t)n * n);
-    col.alloc(n);
+    work.alloc((size_t)64 * (n + 64));
     TS_HIP(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), s));
     launch_dense_assemble_cp(M, lam, d_off.p, d_cp.p, n, d_sf.p, A.p, s);
-    for (int k = 0; k < n; k++) launch_gj_step(A.p, col.p, n, k, s);
+    launch_gj_blocked(A.p, n, work.p, s);
     TS_HIP(hipGetLastError());
     sv->AinvT.alloc((size_t)n * n);
     launch_transpose(A.p, sv->AinvT.p, n, s);

@@ -97,6 +97,8 @@ def lib():
             "or_set_ifem_flags": (None, [P]),
             "or_fallback_flags": (None, [P, I, I, P, D, P]),
             "or_mg_set_flags": (None, [P, I, P]),
+            "or_mg_set_dd": (None, [P, I]),
+            "or_solve_dd": (I, [P, P, P, D, I, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -272,7 +274,7 @@ class Multigrid:
     """V(nu1, nu2) cycle of the oracle on levels N = 2^lam, lam0..lamL."""
 
     def __init__(self, mesh, lam0, lamL, kind=IFEM, q=2, center=0, coeffs=None, nu1=3, nu2=3,
-                 flags=None):
+                 flags=None, dd=False):
         self.mesh = mesh
         self.lam0, self.lamL = lam0, lamL
         nl = lamL - lam0 + 1
@@ -294,6 +296,8 @@ class Multigrid:
                     a = np.ascontiguousarray(flags[l], dtype=np.uint8)
                     self._keep.append(a)
                     lib().or_mg_set_flags(self.h, lam0 + l, _p(a))
+        if dd:
+            lib().or_mg_set_dd(self.h, 1)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -313,6 +317,16 @@ class Multigrid:
         c = lib().or_solve(self.h, _p(f), _p(u), rtol, max_cycles, _p(hist))
         n = c if c >= 0 else max_cycles
         return u, int(c), hist[: n + 1]
+
+    def solve_dd(self, f, u0=None, rtol=1e-10, max_cycles=50):
+        """Cycles until the relative update ||u_c - u_(c-1)|| / ||u_c|| <= rtol
+        (the stop test of double discretisation, Sec. 4.1)."""
+        f = _f64(f)
+        u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
+        hist = np.zeros(max_cycles)
+        c = lib().or_solve_dd(self.h, _p(f), _p(u), rtol, max_cycles, _p(hist))
+        n = c if c >= 0 else max_cycles
+        return u, int(c), hist[:n]
 
 
 _flag_keep = [None]

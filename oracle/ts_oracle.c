@@ -1111,10 +1111,13 @@ void or_coarse_solve(const or_coarse *C, const or_mesh *M, const double *f, doub
 
 /* levels: N = 2^lam for lam = lam0 .. lamL; lam0 uses IFEM and the coarse
    solve; every finer level uses the operator (kind, q, center) with its own
-   coefficients coeffs[lam - lam0] (NULL entries are allowed for IFEM). */
+   coefficients coeffs[lam - lam0] (NULL entries are allowed for IFEM).
+   dd != 0 selects double discretisation (Sec. 4.1): the smoothing sweeps keep
+   the operator (kind, q, center) while every residual r = f - L u uses the
+   exact IFEM operator L. */
 typedef struct {
     const or_mesh *M;
-    int lam0, lamL, kind, q, center, nu1, nu2;
+    int lam0, lamL, kind, q, center, nu1, nu2, dd;
     const double **coeffs;
     const unsigned char **flags;
     or_coarse *coarse;
@@ -1136,6 +1139,8 @@ or_mg *or_mg_new(const or_mesh *M, int lam0, int lamL, int kind, int q, int cent
 void or_mg_set_flags(or_mg *G, int lam, const unsigned char *flags) {
     G->flags[lam - G->lam0] = flags;
 }
+
+void or_mg_set_dd(or_mg *G, int dd) { G->dd = dd; }
 
 void or_mg_free(or_mg *G) {
     if (!G) return;
@@ -1161,7 +1166,10 @@ static void vcycle_rec(const or_mg *G, int lam, const double *f, double *u) {
     double *fc = malloc(sizeof(double) * nc);
     double *uc = calloc(nc, sizeof(double));
     double *e = malloc(sizeof(double) * nf);
-    or_residual(M, N, kind, G->q, G->center, cf, f, u, r);
+    if (G->dd)
+        or_residual(M, N, 0, G->q, G->center, NULL, f, u, r);
+    else
+        or_residual(M, N, kind, G->q, G->center, cf, f, u, r);
     or_restrict(M, N, r, fc);
     vcycle_rec(G, lam - 1, fc, uc);
     or_set_ifem_flags(G->flags[lam - G->lam0]);
@@ -1209,6 +1217,35 @@ int or_solve(const or_mg *G, const double *f, double *u, double rtol,
         if (hist) hist[c] = rel;
     }
     free(r);
+    return rel <= rtol ? c : -1;
+}
+
+/* Double-discretisation solve (Sec. 4.1): with two operators in the cycle the
+   residual does not go to zero, so the stop test is on the update instead,
+   ||u_c - u_{c-1}||_2 <= rtol ||u_c||_2 over the free rows.  Returns the
+   number of cycles (or -1 when max_cycles is reached); hist[c - 1] gets the
+   relative update of cycle c (size max_cycles). */
+int or_solve_dd(const or_mg *G, const double *f, double *u, double rtol,
+                int max_cycles, double *hist) {
+    const or_mesh *M = G->M;
+    int N = 1 << G->lamL;
+    int64_t nu = or_num_unique(M, N);
+    double *prev = malloc(sizeof(double) * nu);
+    double *d = malloc(sizeof(double) * nu);
+    double rel = INFINITY;
+    int c = 0;
+    while (c < max_cycles) {
+        memcpy(prev, u, sizeof(double) * nu);
+        or_vcycle(G, f, u);
+        for (int64_t v = 0; v < nu; v++) d[v] = u[v] - prev[v];
+        double nu_ = or_norm_free(M, N, u);
+        rel = nu_ > 0 ? or_norm_free(M, N, d) / nu_ : 0.0;
+        if (hist) hist[c] = rel;
+        c++;
+        if (rel <= rtol) break;
+    }
+    free(prev);
+    free(d);
     return rel <= rtol ? c : -1;
 }
 

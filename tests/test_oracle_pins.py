@@ -503,3 +503,72 @@ def test_fallback_rows_are_ifem_rows(orc):
         sl = slice(nlow + m * nvol, nlow + (m + 1) * nvol)
         assert np.array_equal(ym[sl], (yi if fl[m] else ys)[sl])
     assert np.array_equal(ym[:nlow], ys[:nlow])
+
+
+# ---------------------------------------------------------------------------
+# double discretisation (Sec. 4.1): surrogate smoothing, exact residuals,
+# stop on the update
+
+
+def test_dd_on_affine_macro_is_the_plain_cycle(orc):
+    # Phi = Id: the fitted surrogate is the exact stencil (remark in Sec.
+    # 3.4), so the mixed cycle and the plain IFEM cycle are the same map
+    v, t = inputs.single_macro()
+    M = orc.Mesh(v, t, affine=True)
+    lam = 4
+    N = 2 ** lam
+    cf = [None] + [M.fit(2 ** l, orc.LSQP, 2, 2) for l in range(3, lam + 1)]
+    f = M.rhs(N, 2)
+    u0 = np.random.default_rng(3).uniform(-1, 1, f.shape) * (M.dirichlet_mask(N) == 0)
+    Gd = orc.Multigrid(M, 2, lam, kind=orc.LSQP, coeffs=cf, dd=True)
+    Gi = orc.Multigrid(M, 2, lam, kind=orc.IFEM)
+    ud, ui = u0, u0
+    for _ in range(3):
+        ud, ui = Gd.vcycle(f, ud), Gi.vcycle(f, ui)
+    assert np.abs(ud - ui).max() < 1e-12 * np.abs(ui).max()
+
+
+@pytest.fixture(scope="module")
+def dd_runs(orc):
+    # 36-macro shell, level 4, manufactured solution: the IFEM solution, the
+    # pure LSQP solution and the double-discretisation fixed point
+    v, t = inputs.shell36()
+    M = orc.Mesh(v, t)
+    lam = 4
+    N = 2 ** lam
+    f = M.rhs(N, 0, [0.55, 1.0])
+    cf = [None] + [M.fit(2 ** l, orc.LSQP, 2, 2) for l in range(3, lam + 1)]
+    ui, ci, _ = orc.Multigrid(M, 2, lam, kind=orc.IFEM).solve(f, rtol=1e-10, max_cycles=60)
+    us, cs, _ = orc.Multigrid(M, 2, lam, kind=orc.LSQP, coeffs=cf).solve(f, rtol=1e-10,
+                                                                          max_cycles=60)
+    Gd = orc.Multigrid(M, 2, lam, kind=orc.LSQP, coeffs=cf, dd=True)
+    ud, cd, hd = Gd.solve_dd(f, rtol=1e-10, max_cycles=60)
+    assert ci > 0 and cs > 0 and cd > 0
+    X = M.coords(N)
+    ue = orc.exact_manufactured(0.55, 1.0, X)
+    V = M.node_volumes(N)
+    err = {k: np.sqrt((V * (u - ue) ** 2).sum()) for k, u in (("ifem", ui), ("lsqp", us),
+                                                                ("dd", ud))}
+    return dict(M=M, N=N, f=f, cf=cf, ud=ud, hd=hd, err=err)
+
+
+def test_dd_recovers_most_of_the_fem_error(orc, dd_runs):
+    # Sec. 4.2: the mixed scheme moves the error of the surrogate solution
+    # most of the way back to that of the exact Galerkin solution
+    e = dd_runs["err"]
+    assert e["ifem"] < e["dd"] < e["lsqp"]
+    assert e["dd"] - e["ifem"] < 0.6 * (e["lsqp"] - e["ifem"])
+
+
+def test_dd_residuals_stall_while_updates_vanish(orc, dd_runs):
+    # Sec. 4.1 / 4.2: the two operators compete, so neither residual goes to
+    # zero at the fixed point; the updates do (geometrically).  A cycle that
+    # smoothed with L would drive ||f - L u|| to zero, one whose residual used
+    # L~ would drive ||f - L~ u|| to zero.
+    M, N, f, ud, hd = (dd_runs[k] for k in ("M", "N", "f", "ud", "hd"))
+    nf = np.linalg.norm(f)
+    rL = np.linalg.norm(M.residual(N, f, ud, kind=orc.IFEM)) / nf
+    rS = np.linalg.norm(M.residual(N, f, ud, kind=orc.LSQP, coeffs=dd_runs["cf"][-1])) / nf
+    assert hd[-1] <= 1e-10
+    assert rL > 1e-3 and rS > 1e-3
+    assert np.all(hd[2:] < 0.5 * hd[1:-1])

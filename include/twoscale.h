@@ -98,15 +98,26 @@ typedef struct {
     double rtol;         /* stop when ||f - L u||_2 <= rtol ||f||_2 (free rows) */
     int diverge_window;  /* stop with TS_ENOCONV after this many consecutive
                             residual increases (0: default 3) */
+    int dd;              /* non-zero: double discretisation (Sec. 4.1).  The
+                            smoothing sweeps use the operator's surrogate
+                            stencils, every residual of the cycle the exact
+                            element-wise (IFEM) rows; the two operators
+                            compete, so the solve stops on the update instead,
+                            ||u_c - u_(c-1)||_2 <= rtol ||u_c||_2 (free rows).
+                            TS_F64 precision only (TS_EINVAL otherwise);
+                            IFEM rows limit it to level 8 */
 } ts_solve_params;
 
 #define TS_MAX_HIST 256
 typedef struct {
     int cycles;          /* outer iterations done */
     int status;          /* TS_OK, TS_ENOCONV or TS_ENONFINITE */
-    double rel_residual; /* final ||f - L u|| / ||f|| in FP64 */
+    double rel_residual; /* final ||f - L u|| / ||f|| in FP64; with dd the
+                            last relative update */
     int n_hist;
-    double hist[TS_MAX_HIST]; /* relative residual before each iteration and at the end */
+    double hist[TS_MAX_HIST]; /* relative residual before each iteration and at
+                                 the end; with dd the relative update of each
+                                 cycle */
 } ts_solve_info;
 
 const char *ts_last_error(void);

@@ -52,7 +52,8 @@ class ts_op_params(C.Structure):
 
 class ts_solve_params(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int),
-                ("precision", C.c_int), ("rtol", C.c_double), ("diverge_window", C.c_int)]
+                ("precision", C.c_int), ("rtol", C.c_double), ("diverge_window", C.c_int),
+                ("dd", C.c_int)]
 
 
 class ts_solve_info(C.Structure):
@@ -242,8 +243,8 @@ def ts_norm2(mesh, level, dtype, x, stream=None):
 
 
 def ts_solver_create(op, level, nu1=3, nu2=3, max_cycles=60, precision=TS_F64, rtol=1e-10,
-                     diverge_window=3):
-    p = ts_solve_params(nu1, nu2, max_cycles, precision, rtol, diverge_window)
+                     diverge_window=3, dd=False):
+    p = ts_solve_params(nu1, nu2, max_cycles, precision, rtol, diverge_window, 1 if dd else 0)
     h = C.c_void_p()
     _check(lib().ts_solver_create(op, level, C.byref(p), C.byref(h)))
     return h

@@ -148,10 +148,11 @@ constexpr int kForkLevel = 6;
 
 // y = L x (mode 0) or y = f - L x (mode 1).  The lower-primitive rows and the
 // volume rows write disjoint slots, so on large levels the former run on the
-// operator's side stream while the volume kernel runs on s.
+// operator's side stream while the volume kernel runs on s.  exact: the
+// volume rows take the element-wise IFEM stencils even on surrogate levels.
 static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                    const void* f, hipStream_t s) {
-    const bool sur = uses_surrogate(op, lam);
+                    const void* f, hipStream_t s, bool exact = false) {
+    const bool sur = !exact && uses_surrogate(op, lam);
     // the face rows run inside the surrogate volume launch when it has work
     const bool fuse = sur && op->lv.at(lam)->n_sur > 0;
     const bool fork = lam >= kForkLevel && op->side;
@@ -320,7 +321,7 @@ static void vcycle_t(ts_solver* sv, int lam, int dtype, const X* f, X* u, hipStr
     const Level& Lc = M.level(lam - 1);
     for (int k = 0; k < sv->p.nu1; k++) gs_sweep(sv->op, lam, dtype, f, u, s);
     X* r = vec(R, lam, Lf.len);
-    op_rows(sv->op, lam, dtype, 1, u, r, f, s);
+    op_rows(sv->op, lam, dtype, 1, u, r, f, s, sv->p.dd != 0);
     X* fc = vec(F, lam - 1, Lc.len);
     X* uc = vec(U, lam - 1, Lc.len);
     launch_restrict(M, lam, vd, r, fc, s);
@@ -588,6 +589,8 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
         TS_REQUIRE(p->max_cycles > 0 && p->max_cycles < TS_MAX_HIST - 1, TS_EINVAL, "bad max_cycles");
         TS_REQUIRE(p->rtol > 0, TS_EINVAL, "rtol must be positive");
         check_dtype(p->precision);
+        TS_REQUIRE(!p->dd || p->precision == TS_F64, TS_EINVAL,
+                   "double discretisation runs in FP64 precision");
         auto* sv = new ts_solver();
         try {
             sv->op = op;
@@ -607,8 +610,8 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
             TS_HIP(hipStreamDestroy(s));
             Mesh& M = op->mesh->m;
             sv->partial.alloc(norm_partial_count(M, level));
-            sv->nrm.alloc(2);
-            TS_HIP(hipHostMalloc((void**)&sv->hnrm, 2 * sizeof(double), hipHostMallocDefault));
+            sv->nrm.alloc(3);
+            TS_HIP(hipHostMalloc((void**)&sv->hnrm, 3 * sizeof(double), hipHostMallocDefault));
             TS_HIP(hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming));
         } catch (...) {
             delete sv;
@@ -658,20 +661,36 @@ static void solve_begin(ts_solver* sv, const double* f, double* u, hipStream_t s
     sv->ups = 0;
     memset(&sv->info, 0, sizeof(sv->info));
     launch_norm2_free(M, sv->L, TS_F64, f, sv->partial.p, sv->nrm.p, st);
-    outer_residual(sv, st);
+    if (!sv->p.dd) outer_residual(sv, st);
     TS_HIP(hipMemcpyAsync(sv->hnrm, sv->nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     TS_HIP(hipEventRecord(sv->ev, st));
     sv->state = TS_SOLVE_RUNNING;
 }
 
 // one outer iteration: FP64 V-cycle on u, or a V-cycle on the rounded
-// residual in FP32 / FP16-weight arithmetic added to u; then the new residual
+// residual in FP32 / FP16-weight arithmetic added to u; then the new residual.
+// Double discretisation: the cycle on u, then the norms of the update
+// (u_prev - u, kept in r_outer) and of u.
 static void solve_step(ts_solver* sv) {
     TS_REQUIRE(sv->state == TS_SOLVE_READY, TS_EINVAL, "the solver is not ready for a step");
     Mesh& M = sv->op->mesh->m;
     const Level& L = M.level(sv->L);
     hipStream_t st = sv->as;
     const int prec = sv->p.precision;
+    if (sv->p.dd) {
+        TS_HIP(hipMemcpyAsync(sv->r_outer.p, sv->au, (size_t)L.len * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+        vcycle(sv, TS_F64, sv->af, sv->au, st);
+        launch_axpy(-1.0, sv->au, TS_F64, sv->r_outer.p, L.len, st);
+        sv->info.cycles++;
+        launch_norm2_free(M, sv->L, TS_F64, sv->r_outer.p, sv->partial.p, sv->nrm.p + 1, st);
+        launch_norm2_free(M, sv->L, TS_F64, sv->au, sv->partial.p, sv->nrm.p + 2, st);
+        TS_HIP(hipMemcpyAsync(sv->hnrm + 1, sv->nrm.p + 1, 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        TS_HIP(hipEventRecord(sv->ev, st));
+        sv->state = TS_SOLVE_RUNNING;
+        return;
+    }
     if (prec == TS_F64) {
         vcycle(sv, TS_F64, sv->af, sv->au, st);
     } else {
@@ -706,12 +725,17 @@ static void solve_advance(ts_solver* sv) {
             return finish(TS_OK);
         }
     }
-    const double rel = sv->hnrm[1] / sv->nf;
+    if (sv->p.dd && I.cycles == 0) {  // nothing to test before the first cycle
+        sv->state = TS_SOLVE_READY;
+        return;
+    }
+    const double rel = !sv->p.dd ? sv->hnrm[1] / sv->nf
+                       : sv->hnrm[2] > 0.0 ? sv->hnrm[1] / sv->hnrm[2] : 0.0;
     I.rel_residual = rel;
     if (I.n_hist < TS_MAX_HIST) I.hist[I.n_hist++] = rel;
     if (!std::isfinite(rel)) return finish(TS_ENONFINITE);
     if (rel <= sv->p.rtol) return finish(TS_OK);
-    if (I.cycles > 0) {
+    if (I.cycles > (sv->p.dd ? 1 : 0)) {
         sv->ups = rel > sv->prev ? sv->ups + 1 : 0;
         if (sv->ups >= sv->p.diverge_window) return finish(TS_ENOCONV);
     }

@@ -98,6 +98,14 @@ def lib():
             "or_fallback_flags": (None, [P, I, I, P, D, P]),
             "or_mg_set_flags": (None, [P, I, P]),
             "or_mg_set_dd": (None, [P, I]),
+            "or_mg_set_face_coeffs": (None, [P, I, P]),
+            "or_set_face_coeffs": (None, [P]),
+            "or_num_coeffs2": (I, [I]),
+            "or_face_sample_points": (I64, [I, I, P]),
+            "or_face_fit": (I, [P, I, I, I, P]),
+            "or_face_row_exact": (I, [P, I, I64, P, P]),
+            "or_face_fit_values": (I, [I, I, I, P, P]),
+            "or_face_poly_eval": (D, [I, I, P, I, I]),
             "or_solve_dd": (I, [P, P, P, D, I, P]),
         }
         for name, (res, args) in sig.items():
@@ -190,17 +198,34 @@ class Mesh:
             raise ValueError("oracle fit failed (method %d, q %d)" % (method, q))
         return c
 
+    def face_fit(self, N, q=2, jsamp=2):
+        """Per-face fits of the rows of interior-face nodes: nf x 15 x m2 in
+        the face frame (zero for faces that are not fitted)."""
+        c = np.zeros((self.nf, NW, num_coeffs2(q)))
+        err = lib().or_face_fit(self.h, N, q, jsamp, _p(c))
+        if err:
+            raise ValueError("oracle face fit failed (q %d)" % q)
+        return c
+
+    def face_row_exact(self, N, u):
+        """Exact 15 entries of the face node u and their unique ids."""
+        s = np.zeros(NW)
+        nb = np.zeros(NW, dtype=np.int64)
+        lib().or_face_row_exact(self.h, N, int(u), _p(s), _p(nb))
+        return s, nb
+
     # --- operator ---------------------------------------------------------
-    def apply(self, N, x, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
-        _set_flags(flags)
+    def apply(self, N, x, kind=IFEM, q=2, center=0, coeffs=None, flags=None, fcoeffs=None):
+        _set_flags(flags, fcoeffs)
         x = _f64(x)
         y = np.zeros_like(x)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
         lib().or_apply(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(x), _p(y))
         return y
 
-    def apply_rows(self, N, x, rows, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
-        _set_flags(flags)
+    def apply_rows(self, N, x, rows, kind=IFEM, q=2, center=0, coeffs=None, flags=None,
+                   fcoeffs=None):
+        _set_flags(flags, fcoeffs)
         x = _f64(x)
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         y = np.zeros(rows.shape[0])
@@ -209,16 +234,18 @@ class Mesh:
                             rows.shape[0], _p(y))
         return y
 
-    def residual(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
-        _set_flags(flags)
+    def residual(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None,
+                 fcoeffs=None):
+        _set_flags(flags, fcoeffs)
         f, u = _f64(f), _f64(u)
         r = np.zeros_like(u)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
         lib().or_residual(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(f), _p(u), _p(r))
         return r
 
-    def gs_sweep(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None):
-        _set_flags(flags)
+    def gs_sweep(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None,
+                 fcoeffs=None):
+        _set_flags(flags, fcoeffs)
         f = _f64(f)
         u = np.array(u, dtype=np.float64, copy=True)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
@@ -274,7 +301,7 @@ class Multigrid:
     """V(nu1, nu2) cycle of the oracle on levels N = 2^lam, lam0..lamL."""
 
     def __init__(self, mesh, lam0, lamL, kind=IFEM, q=2, center=0, coeffs=None, nu1=3, nu2=3,
-                 flags=None, dd=False):
+                 flags=None, dd=False, fcoeffs=None):
         self.mesh = mesh
         self.lam0, self.lamL = lam0, lamL
         nl = lamL - lam0 + 1
@@ -298,6 +325,12 @@ class Multigrid:
                     lib().or_mg_set_flags(self.h, lam0 + l, _p(a))
         if dd:
             lib().or_mg_set_dd(self.h, 1)
+        if fcoeffs is not None:
+            for l in range(nl):
+                if fcoeffs[l] is not None:
+                    a = _f64(fcoeffs[l])
+                    self._keep.append(a)
+                    lib().or_mg_set_face_coeffs(self.h, lam0 + l, _p(a))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -329,11 +362,12 @@ class Multigrid:
         return u, int(c), hist[:n]
 
 
-_flag_keep = [None]
+_flag_keep = [None, None]
 
 
-def _set_flags(flags):
-    """Per-macro IFEM fallback flags for the next operator call (None: none)."""
+def _set_flags(flags, fcoeffs=None):
+    """Per-macro IFEM fallback flags and per-face fits for the next operator
+    call (None: none)."""
     if flags is None:
         _flag_keep[0] = None
         lib().or_set_ifem_flags(None)
@@ -341,6 +375,37 @@ def _set_flags(flags):
         a = np.ascontiguousarray(flags, dtype=np.uint8)
         _flag_keep[0] = a
         lib().or_set_ifem_flags(_p(a))
+    if fcoeffs is None:
+        _flag_keep[1] = None
+        lib().or_set_face_coeffs(None)
+    else:
+        a = _f64(fcoeffs)
+        _flag_keep[1] = a
+        lib().or_set_face_coeffs(_p(a))
+
+
+def num_coeffs2(q):
+    return (q + 1) * (q + 2) // 2
+
+
+def face_sample_points(N, jsamp=2):
+    n = lib().or_face_sample_points(N, jsamp, None)
+    p = np.zeros((n, 2), dtype=np.int32)
+    lib().or_face_sample_points(N, jsamp, _p(p))
+    return p
+
+
+def face_poly_eval(q, N, c, a, b):
+    return float(lib().or_face_poly_eval(q, N, _p(_f64(c)), int(a), int(b)))
+
+
+def face_fit_values(N, vals, q=2, jsamp=2):
+    """Least-squares fit (15 x m2) of values (ns x 15) at the face sampling
+    points."""
+    c = np.zeros((NW, num_coeffs2(q)))
+    if lib().or_face_fit_values(N, q, jsamp, _p(_f64(vals)), _p(c)):
+        raise ValueError("face fit failed")
+    return c
 
 
 def num_coeffs(q):

@@ -730,6 +730,217 @@ int or_fit(const or_mesh *M, int N, int method, int q, int jsamp, double *coeffs
 }
 
 /* ------------------------------------------------------------------------ */
+/* surrogate rows on interior faces (the remark after eq.                    */
+/* numInteriorPoints: the same fitting applies to face nodes)                */
+/* ------------------------------------------------------------------------ */
+
+/* Which face of the macro a face copy (i, j, k) lies on: 0 i = 0, 1 j = 0,
+   2 k = 0, 3 i + j + k = N (exactly one barycentric weight is 0). */
+static int face_type_of(int N, const int c[3]) {
+    if (c[0] == 0) return 0;
+    if (c[1] == 0) return 1;
+    if (c[2] == 0) return 2;
+    (void)N;
+    return 3;
+}
+
+/* signed distance of direction w from face type f: < 0 leaves the macro,
+   0 stays in the face, > 0 points into the macro */
+static int dir_side(int f, int w) {
+    if (f == 0) return DIR[w][0];
+    if (f == 1) return DIR[w][1];
+    if (f == 2) return DIR[w][2];
+    return -(DIR[w][0] + DIR[w][1] + DIR[w][2]);
+}
+
+static int dir_index(int di, int dj, int dk) {
+    for (int w = 0; w < NW; w++)
+        if (DIR[w][0] == di && DIR[w][1] == dj && DIR[w][2] == dk) return w;
+    return -1;
+}
+
+/* The 15 entries of the row of a free node of an interior face, whose two
+   copies are A (the first macro listed for the face) and B: entry 0 the node,
+   entries 1..10 the other directions of A that do not leave A (the six
+   in-face neighbours and four points inside A) in increasing order, entries
+   11..14 the directions of B that point into B, in increasing order.  nbr
+   gets each entry's unique id and dir its Dirichlet flag. */
+typedef struct {
+    int64_t t[2];
+    int c[2][3];
+    int fa, fb;
+    int wa[11], wb[4];
+    int64_t nbr[NW];
+    int dir[NW];
+} face_row;
+
+static void face_row_setup(const or_mesh *M, int N, int64_t u, face_row *F) {
+    int cijk[2][3];
+    copies(M, N, u, F->t, cijk, 2);
+    for (int c = 0; c < 2; c++)
+        for (int d = 0; d < 3; d++) F->c[c][d] = cijk[c][d];
+    F->fa = face_type_of(N, F->c[0]);
+    F->fb = face_type_of(N, F->c[1]);
+    int na = 0, nb = 0;
+    for (int w = 0; w < NW; w++) {
+        if (dir_side(F->fa, w) >= 0) F->wa[na++] = w;
+        if (dir_side(F->fb, w) > 0) F->wb[nb++] = w;
+    }
+    for (int e = 0; e < 11; e++) {
+        int w = F->wa[e];
+        F->nbr[e] = canon_d(M, N, F->t[0], F->c[0][0] + DIR[w][0], F->c[0][1] + DIR[w][1],
+                            F->c[0][2] + DIR[w][2], &F->dir[e]);
+    }
+    for (int e = 0; e < 4; e++) {
+        int w = F->wb[e];
+        F->nbr[11 + e] = canon_d(M, N, F->t[1], F->c[1][0] + DIR[w][0], F->c[1][1] + DIR[w][1],
+                                 F->c[1][2] + DIR[w][2], &F->dir[11 + e]);
+    }
+}
+
+/* exact (element-wise, Sec. 2.3) weights of the 15 entries: the stiffness
+   rows of the fine tetrahedra at both copies, each coupling added to the
+   entry of the node it reaches */
+static void face_row_exact(const or_mesh *M, int N, const face_row *F, double s[NW]) {
+    for (int e = 0; e < NW; e++) s[e] = 0;
+    for (int c = 0; c < 2; c++) {
+        int tl[32][4][3];
+        int nt = tets_at(N, F->c[c], tl);
+        for (int q = 0; q < nt; q++) {
+            double xx[4][3], K[4];
+            for (int v = 0; v < 4; v++)
+                node_xyz(M, N, F->t[c], tl[q][v][0], tl[q][v][1], tl[q][v][2], xx[v]);
+            stiff_row0(xx, K, NULL);
+            s[0] += K[0];
+            for (int v = 1; v < 4; v++) {
+                int w = dir_index(tl[q][v][0] - F->c[c][0], tl[q][v][1] - F->c[c][1],
+                                  tl[q][v][2] - F->c[c][2]);
+                int e = -1;
+                if (c == 0) {
+                    for (int r = 0; r < 11; r++)
+                        if (F->wa[r] == w) e = r;
+                } else if (dir_side(F->fb, w) > 0) {
+                    for (int r = 0; r < 4; r++)
+                        if (F->wb[r] == w) e = 11 + r;
+                } else {
+                    int64_t g = canon_d(M, N, F->t[1], tl[q][v][0], tl[q][v][1], tl[q][v][2],
+                                        NULL);
+                    for (int r = 1; r < 11; r++)
+                        if (F->nbr[r] == g) e = r;
+                }
+                s[e] += K[v];
+            }
+        }
+    }
+}
+
+/* 2D monomials of total degree <= q in the face frame, alpha = a/N - 1/3,
+   beta = b/N - 1/3 (centred on the face), by degree, then by falling power
+   of alpha */
+int or_num_coeffs2(int q) { return (q + 1) * (q + 2) / 2; }
+
+static void basis_row2(int q, int N, int a, int b, double *row) {
+    double al = (double)a / N - 1.0 / 3.0, be = (double)b / N - 1.0 / 3.0;
+    int c = 0;
+    for (int d = 0; d <= q; d++)
+        for (int l = 0; l <= d; l++) row[c++] = ipow(al, d - l) * ipow(be, l);
+}
+
+/* Face sampling points (a, b): the interior points of the face lattice of
+   level m at stride N / 2^(m+2), with m chosen as for the volume fit. */
+int64_t or_face_sample_points(int N, int jsamp, int *pts) {
+    int l = 0;
+    while ((4 << l) < N) l++;
+    int m = jsamp < 1 ? 1 : jsamp;
+    if (m > l) m = l;
+    int Ns = 4 << m, st = N / Ns;
+    int64_t c = 0;
+    for (int b = 1; b <= Ns - 2; b++)
+        for (int a = 1; a <= Ns - 1 - b; a++) {
+            if (pts) {
+                pts[2 * c] = a * st;
+                pts[2 * c + 1] = b * st;
+            }
+            c++;
+        }
+    return c;
+}
+
+/* Fit the 15 entries of every free interior face (two macros, not on the
+   boundary) by least squares over the face sampling points (Householder
+   QR).  fcoef: nf x 15 x m2 (faces not fitted stay 0).  Returns 0 on
+   success. */
+int or_face_fit(const or_mesh *M, int N, int q, int jsamp, double *fcoef) {
+    int m2 = or_num_coeffs2(q);
+    int64_t ns = or_face_sample_points(N, jsamp, NULL);
+    if (ns < m2) return 1;
+    int *pts = malloc(sizeof(int) * 2 * ns);
+    or_face_sample_points(N, jsamp, pts);
+    memset(fcoef, 0, sizeof(double) * M->nf * NW * m2);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t f = 0; f < M->nf; f++) {
+        if (M->face_count[f] != 2 || M->fdir[f]) continue;
+        double *A = malloc(sizeof(double) * ns * m2);
+        double *B = malloc(sizeof(double) * ns * NW);
+        double *X = malloc(sizeof(double) * m2 * NW);
+        for (int64_t s = 0; s < ns; s++) {
+            int a = pts[2 * s], b = pts[2 * s + 1];
+            int64_t u = M->nv + M->ne * (N - 1) + f * n_face_int(N) + face_off(N, a, b);
+            face_row F;
+            face_row_setup(M, N, u, &F);
+            face_row_exact(M, N, &F, B + s * NW);
+            basis_row2(q, N, a, b, A + s * m2);
+        }
+        err |= householder_lsq((int)ns, m2, A, B, NW, X);
+        for (int e = 0; e < NW; e++)
+            for (int c = 0; c < m2; c++) fcoef[(f * NW + e) * m2 + c] = X[c * NW + e];
+        free(A); free(B); free(X);
+    }
+    free(pts);
+    return err;
+}
+
+/* value at face node (a, b) of the 2D polynomial with coefficients c (m2) */
+double or_face_poly_eval(int q, int N, const double *c, int a, int b) {
+    double row[64];
+    basis_row2(q, N, a, b, row);
+    double s = 0;
+    for (int k = 0; k < or_num_coeffs2(q); k++) s += c[k] * row[k];
+    return s;
+}
+
+/* The same least-squares fit for given values at the face sampling points
+   (ns x 15, row-major); out: 15 x m2.  Returns 0 on success. */
+int or_face_fit_values(int N, int q, int jsamp, const double *vals, double *out) {
+    int m2 = or_num_coeffs2(q);
+    int64_t ns = or_face_sample_points(N, jsamp, NULL);
+    if (ns < m2) return 1;
+    int *pts = malloc(sizeof(int) * 2 * ns);
+    or_face_sample_points(N, jsamp, pts);
+    double *A = malloc(sizeof(double) * ns * m2);
+    double *B = malloc(sizeof(double) * ns * NW);
+    double *X = malloc(sizeof(double) * m2 * NW);
+    for (int64_t s = 0; s < ns; s++) basis_row2(q, N, pts[2 * s], pts[2 * s + 1], A + s * m2);
+    memcpy(B, vals, sizeof(double) * ns * NW);
+    int err = householder_lsq((int)ns, m2, A, B, NW, X);
+    for (int e = 0; e < NW; e++)
+        for (int c = 0; c < m2; c++) out[e * m2 + c] = X[c * NW + e];
+    free(pts); free(A); free(B); free(X);
+    return err;
+}
+
+/* the exact 15 entries of a face node (unique id u), for checks */
+int or_face_row_exact(const or_mesh *M, int N, int64_t u, double *s, int64_t *nbr) {
+    face_row F;
+    face_row_setup(M, N, u, &F);
+    face_row_exact(M, N, &F, s);
+    if (nbr)
+        for (int e = 0; e < NW; e++) nbr[e] = F.nbr[e];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* the operator                                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -741,6 +952,8 @@ typedef struct {
     int kind, q, center;
     const double *coeffs;
     const unsigned char *ifem; /* per macro: 1 = IFEM rows on the volume (NULL: none) */
+    const double *fcoef;       /* kind 1: per-face fits (nf x 15 x m2) for the rows
+                                  of interior faces; NULL: IFEM rows there */
 } or_op;
 
 static int64_t vol_base(const or_mesh *M, int N) {
@@ -807,6 +1020,28 @@ static void row_surrogate(const or_mesh *M, int N, const or_op *op, int64_t t, i
     *off = of;
 }
 
+/* Surrogate row of a free node (a, b) of the interior face f: every entry
+   from its fitted 2D polynomial, the centre from its own polynomial. */
+static void row_face_surrogate(const or_mesh *M, int N, const or_op *op, int64_t u, int64_t f,
+                               int a, int b, const double *x, double *diag, double *off) {
+    int m2 = or_num_coeffs2(op->q);
+    double row[64];
+    basis_row2(op->q, N, a, b, row);
+    face_row F;
+    face_row_setup(M, N, u, &F);
+    const double *fc = op->fcoef + f * NW * m2;
+    double of = 0;
+    for (int e = 1; e < NW; e++) {
+        double se = 0;
+        for (int c = 0; c < m2; c++) se += fc[e * m2 + c] * row[c];
+        of += se * (F.dir[e] ? 0.0 : x[F.nbr[e]]);
+    }
+    double s0 = 0;
+    for (int c = 0; c < m2; c++) s0 += fc[c] * row[c];
+    *diag = s0;
+    *off = of;
+}
+
 /* row of the interior node (i, j, k) of macro t under op */
 static void row_volume(const or_mesh *M, int N, const or_op *op, int64_t t, int i, int j,
                        int k, const double *x, double *diag, double *off) {
@@ -825,6 +1060,10 @@ static void row_eval(const or_mesh *M, int N, const or_op *op, int64_t u,
     or_node n = decode(M, N, u);
     if (n.kind == 3) {
         row_volume(M, N, op, n.prim, n.i, n.j, n.k, x, diag, off);
+        return;
+    }
+    if (n.kind == 2 && op->kind == 1 && op->fcoef && M->face_count[n.prim] == 2) {
+        row_face_surrogate(M, N, op, u, n.prim, n.a, n.b, x, diag, off);
         return;
     }
     int64_t ct[256];
@@ -892,10 +1131,15 @@ static void zero_dirichlet(const or_mesh *M, int N, double *y) {
 static const unsigned char *g_flags = NULL;
 void or_set_ifem_flags(const unsigned char *flags) { g_flags = flags; }
 
+/* Per-face fits used by the surrogate operator entry points below (set with
+   or_set_face_coeffs; NULL: element-wise rows on every face). */
+static const double *g_fcoef = NULL;
+void or_set_face_coeffs(const double *fcoef) { g_fcoef = fcoef; }
+
 /* y = L x over the free rows; Dirichlet rows of y are set to 0. */
 void or_apply(const or_mesh *M, int N, int kind, int q, int center,
               const double *coeffs, const double *x, double *y) {
-    or_op op = {kind, q, center, coeffs, g_flags};
+    or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
     rows_ctx c = {x, NULL, y};
     zero_dirichlet(M, N, y);
     for_rows(M, N, &op, x, -1, cb_apply, &c);
@@ -905,7 +1149,7 @@ void or_apply(const or_mesh *M, int N, int kind, int q, int center,
 void or_apply_rows(const or_mesh *M, int N, int kind, int q, int center,
                    const double *coeffs, const double *x, const int64_t *rows,
                    int64_t nrows, double *y) {
-    or_op op = {kind, q, center, coeffs, g_flags};
+    or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t r = 0; r < nrows; r++) {
         int64_t u = rows[r];
@@ -919,7 +1163,7 @@ void or_apply_rows(const or_mesh *M, int N, int kind, int q, int center,
 /* r = f - L u on the free rows, 0 on Dirichlet rows. */
 void or_residual(const or_mesh *M, int N, int kind, int q, int center,
                  const double *coeffs, const double *f, const double *u, double *r) {
-    or_op op = {kind, q, center, coeffs, g_flags};
+    or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
     rows_ctx c = {u, f, r};
     zero_dirichlet(M, N, r);
     for_rows(M, N, &op, u, -1, cb_residual, &c);
@@ -930,7 +1174,7 @@ void or_residual(const or_mesh *M, int N, int kind, int q, int center,
    of that phase. */
 void or_gs_sweep(const or_mesh *M, int N, int kind, int q, int center,
                  const double *coeffs, const double *f, double *u) {
-    or_op op = {kind, q, center, coeffs, g_flags};
+    or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
     int64_t nu = or_num_unique(M, N);
     int64_t vb = vol_base(M, N);
     int64_t V = n_vol_int(N);
@@ -1120,6 +1364,7 @@ typedef struct {
     int lam0, lamL, kind, q, center, nu1, nu2, dd;
     const double **coeffs;
     const unsigned char **flags;
+    const double **fcoef;
     or_coarse *coarse;
 } or_mg;
 
@@ -1131,6 +1376,7 @@ or_mg *or_mg_new(const or_mesh *M, int lam0, int lamL, int kind, int q, int cent
     int nl = lamL - lam0 + 1;
     G->coeffs = calloc(nl, sizeof(double *));
     G->flags = calloc(nl, sizeof(unsigned char *));
+    G->fcoef = calloc(nl, sizeof(double *));
     for (int l = 0; l < nl; l++) G->coeffs[l] = coeffs ? coeffs[l] : NULL;
     G->coarse = or_coarse_new(M, 1 << lam0);
     return G;
@@ -1142,11 +1388,16 @@ void or_mg_set_flags(or_mg *G, int lam, const unsigned char *flags) {
 
 void or_mg_set_dd(or_mg *G, int dd) { G->dd = dd; }
 
+void or_mg_set_face_coeffs(or_mg *G, int lam, const double *fcoef) {
+    G->fcoef[lam - G->lam0] = fcoef;
+}
+
 void or_mg_free(or_mg *G) {
     if (!G) return;
     or_coarse_free(G->coarse);
     free(G->coeffs);
     free(G->flags);
+    free(G->fcoef);
     free(G);
 }
 
@@ -1160,6 +1411,7 @@ static void vcycle_rec(const or_mg *G, int lam, const double *f, double *u) {
     int kind = G->kind;
     const double *cf = G->coeffs[lam - G->lam0];
     or_set_ifem_flags(G->flags[lam - G->lam0]);
+    or_set_face_coeffs(G->fcoef[lam - G->lam0]);
     for (int s = 0; s < G->nu1; s++) or_gs_sweep(M, N, kind, G->q, G->center, cf, f, u);
     int64_t nf = or_num_unique(M, N), nc = or_num_unique(M, N / 2);
     double *r = malloc(sizeof(double) * nf);
@@ -1173,6 +1425,7 @@ static void vcycle_rec(const or_mg *G, int lam, const double *f, double *u) {
     or_restrict(M, N, r, fc);
     vcycle_rec(G, lam - 1, fc, uc);
     or_set_ifem_flags(G->flags[lam - G->lam0]);
+    or_set_face_coeffs(G->fcoef[lam - G->lam0]);
     or_prolongate(M, N, uc, e);
     for (int64_t v = 0; v < nf; v++) u[v] += e[v];
     for (int s = 0; s < G->nu2; s++) or_gs_sweep(M, N, kind, G->q, G->center, cf, f, u);
@@ -1204,6 +1457,7 @@ int or_solve(const or_mg *G, const double *f, double *u, double rtol,
     const double *cf = G->coeffs[G->lamL - G->lam0];
     double nf = or_norm_free(M, N, f);
     or_set_ifem_flags(G->flags[G->lamL - G->lam0]);
+    or_set_face_coeffs(G->fcoef[G->lamL - G->lam0]);
     or_residual(M, N, G->kind, G->q, G->center, cf, f, u, r);
     double rel = or_norm_free(M, N, r) / nf;
     if (hist) hist[0] = rel;
@@ -1211,6 +1465,7 @@ int or_solve(const or_mg *G, const double *f, double *u, double rtol,
     while (rel > rtol && c < max_cycles) {
         or_vcycle(G, f, u);
         or_set_ifem_flags(G->flags[G->lamL - G->lam0]);
+        or_set_face_coeffs(G->fcoef[G->lamL - G->lam0]);
         or_residual(M, N, G->kind, G->q, G->center, cf, f, u, r);
         rel = or_norm_free(M, N, r) / nf;
         c++;

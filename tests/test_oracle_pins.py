@@ -572,3 +572,88 @@ def test_dd_residuals_stall_while_updates_vanish(orc, dd_runs):
     assert hd[-1] <= 1e-10
     assert rL > 1e-3 and rS > 1e-3
     assert np.all(hd[2:] < 0.5 * hd[1:-1])
+
+
+# ---------------------------------------------------------------------------
+# surrogate rows on interior faces (remark after eq. numInteriorPoints: the
+# fitting applies to face nodes as well)
+
+
+def _face_rows(M, N):
+    nvb = M.nv + M.ne * (N - 1)
+    return nvb, nvb + M.nf * (N - 1) * (N - 2) // 2
+
+
+def test_face_row_entries_reproduce_the_ifem_row(orc):
+    # the 15 entries of a face row (centre, A's in-face and inward directions,
+    # B's inward directions) carry exactly the element-wise row: summed
+    # against x they give the IFEM row value
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t)
+    N = 8
+    x = inputs.uniform(M.num_unique(N), 4)
+    x[M.dirichlet_mask(N)] = 0.0
+    lo, hi = _face_rows(M, N)
+    mask = M.dirichlet_mask(N)
+    rows = np.array([u for u in range(lo, hi, 7) if not mask[u]])
+    yo = M.apply_rows(N, x, rows, kind=orc.IFEM)
+    for r, y in zip(rows, yo):
+        s, nb = M.face_row_exact(N, r)
+        assert len(set(nb.tolist())) == 15
+        assert abs(np.dot(s, x[nb]) - y) < 1e-13 * max(1.0, abs(y))
+        assert abs(s.sum()) < 1e-13 * np.abs(s).max()
+
+
+def test_face_fit_recovers_2d_polynomials(orc):
+    # a degree-q field in the face frame is recovered exactly; the field is
+    # built here in raw powers of (a/N, b/N), not in the fit's centred basis
+    rng = np.random.default_rng(8)
+    N = 32
+    pts = orc.face_sample_points(N, 2)
+    for q in (1, 2, 3, 4):
+        exps = [(d - l, l) for d in range(q + 1) for l in range(d + 1)]
+        C = rng.uniform(-1, 1, (15, len(exps)))
+
+        def field(a, b):
+            return np.array([sum(C[e, k] * (a / N) ** p * (b / N) ** r
+                                 for k, (p, r) in enumerate(exps)) for e in range(15)])
+        vals = np.array([field(a, b) for a, b in pts])
+        c = orc.face_fit_values(N, vals, q=q)
+        for a, b in [(1, 1), (5, 20), (30, 1), (11, 13)]:
+            got = np.array([orc.face_poly_eval(q, N, c[e], a, b) for e in range(15)])
+            assert np.abs(got - field(a, b)).max() < 1e-12
+
+
+def test_face_surrogate_on_affine_mesh_is_exact(orc):
+    # Phi = Id: every face row is constant along its face, so the fitted rows
+    # are the exact ones and the whole surrogate operator is the IFEM one
+    v, t = inputs.shell36()
+    M = orc.Mesh(v, t, affine=True)
+    N = 16
+    cf = M.fit(N, orc.LSQP, 2, 2)
+    fc = M.face_fit(N, q=2)
+    x = inputs.uniform(M.num_unique(N), 6)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    ys = M.apply(N, x, kind=orc.LSQP, q=2, coeffs=cf, fcoeffs=fc)
+    assert np.abs(ys - yi).max() < 1e-12 * np.abs(yi).max()
+
+
+def test_face_surrogate_row_sums_and_degree(orc):
+    # Lemma (zero row sums carry over to the fit, which is linear in the
+    # data): the 15 fitted polynomials of a face sum to zero.  The face-row
+    # error to the exact rows falls with the degree, as for the volume.
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t)
+    N = 16
+    x = inputs.uniform(M.num_unique(N), 7)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    lo, hi = _face_rows(M, N)
+    errs = []
+    for q in (1, 2, 3, 4):
+        fc = M.face_fit(N, q=q)
+        assert np.abs(fc.sum(axis=1)).max() < 1e-12 * np.abs(fc).max()
+        cf = M.fit(N, orc.LSQP, q, 2)
+        ys = M.apply(N, x, kind=orc.LSQP, q=q, coeffs=cf, fcoeffs=fc)
+        errs.append(np.abs(ys - yi)[lo:hi].max() / np.abs(yi[lo:hi]).max())
+    assert errs[0] > 2 * errs[1] > 4 * errs[2] > 8 * errs[3] > 0
+    assert errs[1] < 0.1

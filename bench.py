@@ -264,6 +264,28 @@ def main():
                          "volume_gbs": round(alg_bytes / (q4_vol / 1e3) / 1e9, 1)}
     log("q=4 apply: %.3f ms (volume %.3f ms)" % (q4_ms, q4_vol))
     del op4
+    # q = 2 with surrogate rows on the interior faces as well (FP64 apply,
+    # residual and Gauss-Seidel sweep); its largest relative deviation from
+    # the operator with exact face rows on this x
+    opF = ts.Operator(G, lam, method=ts.TS_LSQP, q=q, sample_j=2, face_surrogate=True)
+    yF = torch.zeros_like(xb)
+    ts.ts_apply(opF.h, lam, ts.TS_F64, xb, yF, stream)
+    fs_ms = time_events(lambda: ts.ts_apply(opF.h, lam, ts.TS_F64, xb, yF, stream), reps, stream)
+    ts.ts_apply(op.h, lam, ts.TS_F64, xb, yb, stream)
+    torch.cuda.synchronize()
+    fs_dev = float((yF - yb).abs().max() / yb.abs().max())
+    rF = torch.zeros_like(xb)
+    fs_res = time_events(lambda: ts.ts_residual(opF.h, lam, ts.TS_F64, xb, xb, rF, stream), reps,
+                         stream)
+    uF = xb.clone()
+    fs_gs = time_events(lambda: ts.ts_smooth(opF.h, lam, ts.TS_F64, xb, uF, 1, stream), 5, stream)
+    extra["face_surrogate_apply"] = {
+        "ms": round(fs_ms, 4), "gdofs": round(info.n_free / fs_ms / 1e6, 3),
+        "residual_ms": round(fs_res, 4), "gs_sweep_ms": round(fs_gs, 4),
+        "max_rel_dev_vs_exact_face_rows": fs_dev}
+    log("face-surrogate apply: %.3f ms (%.2f GDoF/s), residual %.3f ms, GS sweep %.3f ms, "
+        "deviation %.2e" % (fs_ms, info.n_free / fs_ms / 1e6, fs_res, fs_gs, fs_dev))
+    del opF, yF, rF, uF
     # FP32 and FP16-weight applies, residual, Gauss-Seidel sweeps
     x32 = xb.float()
     y32 = torch.zeros_like(x32)

@@ -88,6 +88,20 @@ typedef struct {
                             (1,1,N-3), (N/4,N/4,N/4) its surrogate centre
                             weight is <= 0 or differs from the exact one by
                             more than fallback_tol times it; <= 0: never */
+    int face_surrogate;  /* non-zero: the rows of free interior-face nodes also
+                            come from surrogate polynomials (the remark after
+                            eq. numInteriorPoints): per face and level each of
+                            the 15 row entries (the node, the other
+                            directions of its first macro that stay in it,
+                            the inward directions of the second macro) is a
+                            2D polynomial of degree q in the face, fitted by
+                            least squares to the exact rows at the face nodes
+                            of the LSQP sampling lattice (m = min(l, max(1,
+                            sample_j))); centre from its own polynomial.  On
+                            levels where the selective surrogate keeps IFEM
+                            volume rows on some macro, and in exact residuals,
+                            every face keeps its exact rows.  0: exact face
+                            rows (default) */
 } ts_op_params;
 
 typedef struct {

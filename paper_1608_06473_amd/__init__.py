@@ -47,7 +47,7 @@ class ts_layout_info(C.Structure):
 
 class ts_op_params(C.Structure):
     _fields_ = [("method", C.c_int), ("q", C.c_int), ("sample_j", C.c_int), ("center", C.c_int),
-                ("fallback_tol", C.c_double)]
+                ("fallback_tol", C.c_double), ("face_surrogate", C.c_int)]
 
 
 class ts_solve_params(C.Structure):
@@ -184,8 +184,8 @@ def ts_rhs(mesh, level, kind, params, f, stream=None):
 
 
 def ts_op_create(mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 fallback_tol=0.0, stream=None):
-    p = ts_op_params(method, q, sample_j, center, fallback_tol)
+                 fallback_tol=0.0, stream=None, face_surrogate=False):
+    p = ts_op_params(method, q, sample_j, center, fallback_tol, 1 if face_surrogate else 0)
     h = C.c_void_p()
     _check(lib().ts_op_create(mesh, max_level, C.byref(p), _stream(stream), C.byref(h)))
     return h
@@ -350,12 +350,12 @@ class Operator:
     """Owning wrapper of a ts_op handle (keeps its mesh alive)."""
 
     def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 fallback_tol=0.0, stream=None):
+                 fallback_tol=0.0, stream=None, face_surrogate=False):
         self.mesh = mesh
         self.method, self.q = method, q
         self.max_level = max_level
         self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol,
-                              stream)
+                              stream, face_surrogate)
 
     def macro_flags(self, level):
         """1 for macros whose volume rows stay IFEM on this level."""

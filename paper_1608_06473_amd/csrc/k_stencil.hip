@@ -82,15 +82,161 @@ __global__ __launch_bounds__(256) void k_zero_slots(T* __restrict__ y,
     if (t < n) y[slots[t]] = (T)0;
 }
 
-// Same modes as k_iface; list (optional) selects positions.
-template <typename T, int MODE>
+// Same modes as k_iface; list (optional) selects positions; FQ > 0 takes
+// the face fits of that degree instead of the stored rows.
+template <typename T, int MODE, int FQ>
 __global__ __launch_bounds__(256) void k_face2(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
-    const int4* __restrict__ cp, const double* __restrict__ sten, int n2,
-    const int* __restrict__ list, int n, int N, int64_t B, double* __restrict__ tmp) {
+    const int4* __restrict__ cp, const double* __restrict__ sten,
+    const double* __restrict__ fcoef, int n2, const int* __restrict__ list, int n, int N,
+    int64_t B, double* __restrict__ tmp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    face2_node<T, MODE>(x, y, f, cp, sten, n2, list, t, N, B, tmp);
+    face2_node<T, MODE, FQ>(x, y, f, cp, sten, fcoef, n2, list, t, N, B, tmp);
+}
+
+// Least-squares fit of the face rows of one interior face per workgroup: the
+// exact combined rows at the sampling lattice (the face nodes whose
+// barycentric weights are all multiples of st = N / Ns, Ns = 2^(m+2)) are
+// staged in LDS in chunks; each thread accumulates entries of the normal
+// equations (Gram matrix of the face basis, and its products with the 15
+// entries); one thread then solves them by Cholesky.  Sample s runs over the
+// Ns lattice by b' = 1 .. Ns-2, a' = 1 .. Ns-1-b' in the face frame, where
+// the node (a, b) = (a' st, b' st) sits at (b-1)(N-1) - (b-1) b / 2 + a-1 in
+// the face's range.
+template <int FQ>
+__global__ __launch_bounds__(256) void k_face_fit(const int4* __restrict__ cp,
+                                                  const double* __restrict__ sten, int n2,
+                                                  const int* __restrict__ foff, int N, int Ns,
+                                                  double* __restrict__ fcoef) {
+    constexpr int M2 = FaceBasis<FQ>::M2;
+    constexpr int NG = M2 * (M2 + 1) / 2, NE = NG + M2 * NW;
+    constexpr int CH = 128, PER = (NE + 255) / 256;
+    __shared__ double sphi[CH][M2];
+    __shared__ double sw[CH][NW];
+    __shared__ double sys[NE];
+    __shared__ double R[M2][M2], X[M2][NW];
+    const int tid = (int)threadIdx.x;
+    const int off = foff[blockIdx.x];
+    const int st = N / Ns, ns = (Ns - 1) * (Ns - 2) / 2;
+    // entry e < NG: Gram (r, c), r <= c; else right-hand side (r, w)
+    int er[PER], ec[PER];
+#pragma unroll
+    for (int p = 0; p < PER; p++) {
+        const int e = tid + p * 256;
+        er[p] = -1;
+        ec[p] = 0;
+        if (e < NG) {
+            int r = 0, rem = e;
+            while (rem >= M2 - r) {
+                rem -= M2 - r;
+                r++;
+            }
+            er[p] = r;
+            ec[p] = r + rem;
+        } else if (e < NE) {
+            er[p] = (e - NG) / NW;
+            ec[p] = M2 + (e - NG) % NW;
+        }
+    }
+    double acc[PER];
+#pragma unroll
+    for (int p = 0; p < PER; p++) acc[p] = 0.0;
+    for (int c0 = 0; c0 < ns; c0 += CH) {
+        const int sidx = c0 + tid;
+        if (tid < CH && sidx < ns) {
+            int bq = 1, r = sidx;
+            while (r >= Ns - 1 - bq) {
+                r -= Ns - 1 - bq;
+                bq++;
+            }
+            const int a = (r + 1) * st, b = bq * st;
+            const int q = off + (b - 1) * (N - 1) - (b - 1) * b / 2 + a - 1;
+            const int4 ca = cp[q];
+            const int fa = face_type(N, ca.y, ca.z, ca.w);
+            const double invN = 1.0 / (double)N;
+            const double u = (double)(fa == 0 ? ca.z : ca.y) * invN - 1.0 / 3.0;
+            const double v = (double)(fa <= 1 ? ca.w : ca.z) * invN - 1.0 / 3.0;
+            double phi[M2];
+            face_phi<FQ>(u, v, phi);
+#pragma unroll
+            for (int c = 0; c < M2; c++) sphi[tid][c] = phi[c];
+#pragma unroll
+            for (int e = 0; e < NW; e++) sw[tid][e] = sten[(size_t)e * n2 + q];
+        }
+        __syncthreads();
+        const int nc = min(CH, ns - c0);
+#pragma unroll
+        for (int p = 0; p < PER; p++) {
+            if (er[p] < 0) continue;
+            double a = acc[p];
+            for (int k = 0; k < nc; k++)
+                a += sphi[k][er[p]] * (ec[p] < M2 ? sphi[k][ec[p]] : sw[k][ec[p] - M2]);
+            acc[p] = a;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < PER; p++)
+        if (er[p] >= 0) sys[tid + p * 256] = acc[p];
+    __syncthreads();
+    if (tid != 0) return;
+    // Gram G (upper triangle, row-packed) -> Cholesky G = R^T R in place
+    for (int r = 0, e = 0; r < M2; r++)
+        for (int c = r; c < M2; c++, e++) R[r][c] = sys[e];
+    for (int r = 0; r < M2; r++)
+        for (int w = 0; w < NW; w++) X[r][w] = sys[NG + r * NW + w];
+    for (int r = 0; r < M2; r++) {
+        double d = R[r][r];
+        for (int k = 0; k < r; k++) d -= R[k][r] * R[k][r];
+        d = sqrt(d);
+        R[r][r] = d;
+        for (int c = r + 1; c < M2; c++) {
+            double v = R[r][c];
+            for (int k = 0; k < r; k++) v -= R[k][r] * R[k][c];
+            R[r][c] = v / d;
+        }
+    }
+    // R^T z = rhs, then R x = z, for the 15 entries
+    for (int w = 0; w < NW; w++) {
+        for (int r = 0; r < M2; r++) {
+            double v = X[r][w];
+            for (int k = 0; k < r; k++) v -= R[k][r] * X[k][w];
+            X[r][w] = v / R[r][r];
+        }
+        for (int r = M2 - 1; r >= 0; r--) {
+            double v = X[r][w];
+            for (int k = r + 1; k < M2; k++) v -= R[r][k] * X[k][w];
+            X[r][w] = v / R[r][r];
+        }
+    }
+    const int4 c0 = cp[off];
+    double* out = fcoef + ((size_t)c0.x * 4 + face_type(N, c0.y, c0.z, c0.w)) * (NW * M2);
+    for (int w = 0; w < NW; w++)
+        for (int c = 0; c < M2; c++) out[w * M2 + c] = X[c][w];
+}
+
+void launch_face_fit(const Level& L, int q, int jsamp, int nt, double* fcoef, hipStream_t s) {
+    const int N = L.N;
+    int l = 0;
+    while ((4 << l) < N) l++;
+    const int m = std::min(l, std::max(1, jsamp));
+    const int Ns = 4 << m;
+    TS_REQUIRE((Ns - 1) * (Ns - 2) / 2 >= (q + 1) * (q + 2) / 2, TS_EINVAL,
+               "face sampling set smaller than the polynomial space");
+    TS_HIP(hipMemsetAsync(fcoef, 0, (size_t)nt * 4 * NW * ((q + 1) * (q + 2) / 2) * sizeof(double), s));
+    if (L.n_f2_faces == 0) return;
+    const unsigned g = (unsigned)L.n_f2_faces;
+#define TS_FF(Q) k_face_fit<Q><<<g, 256, 0, s>>>(L.f2_cp.p, L.f2_sten.p, L.n_f2, L.f2_face_off.p, N, Ns, fcoef)
+    switch (q) {
+        case 1: TS_FF(1); break;
+        case 2: TS_FF(2); break;
+        case 3: TS_FF(3); break;
+        case 4: TS_FF(4); break;
+        default: throw Error{TS_EINVAL, "unsupported surrogate degree"};
+    }
+#undef TS_FF
+    TS_HIP(hipGetLastError());
 }
 
 // Combined face stencils: the element-wise partial stencils of both copies,
@@ -189,7 +335,7 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
     void launch_surr_q##Q##_k##K(const Level& L, int nt, const LevelOp& lo, int dtype,    \
                                  int center, int mode, const void* x, void* y,            \
                                  const void* f, int colour, hipStream_t s,                \
-                                 const double* f2sten);
+                                 const double* f2sten, const double* f2coef);
 TS_DECL(1, 2) TS_DECL(1, 4) TS_DECL(1, 8)
 TS_DECL(2, 2) TS_DECL(2, 4) TS_DECL(2, 8)
 TS_DECL(3, 2) TS_DECL(3, 4) TS_DECL(3, 8)
@@ -210,7 +356,8 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     TS_REQUIRE(L.lds_kpt <= 8, TS_EINVAL, "level too large for the surrogate volume kernel");
     // face rows fused into the launch (apply / residual); built on first use
     const double* f2 = fuse_face && mode != 2 && L.n_f2 ? face_stencils(M, lam, s) : nullptr;
-#define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s, f2)
+    const double* fc = f2 && lo.face_fit ? lo.fcoef.p : nullptr;
+#define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s, f2, fc)
     switch (q * 16 + kpt) {
         case 18: TS_GO(1, 2); break;
         case 20: TS_GO(1, 4); break;
@@ -265,10 +412,14 @@ void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const voi
 // phase >= 0 computes the Gauss-Seidel values of that phase into tmp (face
 // fast path first, then the general nodes after it in tmp).
 void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face) {
+                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face,
+                  bool exact) {
     Mesh& M = op->mesh->m;
     const Level& L = M.level(lam);
     face_stencils(M, lam, s);
+    const LevelOp* lo = op->lv.count(lam) ? op->lv.at(lam).get() : nullptr;
+    const int fq = !exact && lo && lo->face_fit ? op->p.q : 0;
+    const double* fc = fq ? lo->fcoef.p : nullptr;
     // apply / residual: canonical order; Gauss-Seidel phase: its contiguous
     // range of the phase-grouped copy
     const int go = phase >= 0 ? L.f2g_off[phase] : 0;
@@ -278,10 +429,20 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
     double* tmp_r = tmp ? tmp + n2 : nullptr;
+#define TS_F2Q(T_, M_, Q_)                                                                    \
+    k_face2<T_, M_, Q_><<<(n2 + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,   \
+                                                         cp2, sten, fc, L.n_f2, nullptr, n2,  \
+                                                         L.N, L.B, tmp)
 #define TS_F2(T_, M_)                                                                         \
-    k_face2<T_, M_><<<(n2 + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,       \
-                                                     cp2, sten, L.n_f2, nullptr, n2, L.N,     \
-                                                     L.B, tmp)
+    do {                                                                                      \
+        switch (fq) {                                                                         \
+            case 0: TS_F2Q(T_, M_, 0); break;                                                 \
+            case 1: TS_F2Q(T_, M_, 1); break;                                                 \
+            case 2: TS_F2Q(T_, M_, 2); break;                                                 \
+            case 3: TS_F2Q(T_, M_, 3); break;                                                 \
+            default: TS_F2Q(T_, M_, 4); break;                                                \
+        }                                                                                     \
+    } while (0)
 #define TS_IF(T_, M_)                                                                         \
     k_iface<T_, M_><<<(nr + 3) / 4, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,           \
                                                      L.if_off.p, L.if_copy.p, L.rc_base.p,    \
@@ -309,6 +470,7 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
             k_zero_slots<float><<<g, 256, 0, s>>>((float*)y, L.dir_slots.p, L.n_dir_slots);
     }
 #undef TS_F2
+#undef TS_F2Q
 #undef TS_IF
     TS_HIP(hipGetLastError());
 }

@@ -88,6 +88,20 @@ static void split_macros(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
     lo.n_ifem = (int)ifem.size();
     if (lo.n_sur) lo.sur_list.upload(sur); else lo.sur_list.reset();
     if (lo.n_ifem) lo.ifem_list.upload(ifem); else lo.ifem_list.reset();
+    // face fits: only where every volume keeps its surrogate
+    lo.face_fit = lo.fcoef.p && lo.n_ifem == 0;
+}
+
+// Surrogate rows of the level's interior faces, fitted to the exact face rows
+// (built here on s if they do not exist yet).
+static void setup_face_fit(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
+    Mesh& M = op->mesh->m;
+    const Level& L = M.level(lam);
+    face_stencils(M, lam, s);
+    const int m2 = (op->p.q + 1) * (op->p.q + 2) / 2;
+    lo.fcoef.alloc((size_t)M.nt * 4 * NW * m2);
+    launch_face_fit(L, op->p.q, op->p.sample_j, (int)M.nt, lo.fcoef.p, s);
+    TS_HIP(hipStreamSynchronize(s));
 }
 
 static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vector<double>& h) {
@@ -125,6 +139,7 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         TS_HIP(hipStreamSynchronize(s));
         for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite surrogate coefficient");
         upload_coef_variants(op, *lo, lam, h);
+        if (op->p.face_surrogate) setup_face_fit(op, *lo, lam, s);
         split_macros(op, *lo, lam, s);
     }
     op->lv[lam] = std::move(lo);
@@ -161,10 +176,10 @@ static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x
     if (fork) {
         TS_HIP(hipEventRecord(op->ev_fork, s));
         TS_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, op->side, fuse);
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, op->side, fuse, exact);
         TS_HIP(hipEventRecord(op->ev_join, op->side));
     } else {
-        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s, fuse);
+        launch_iface(op, lam, dtype, mode, x, y, f, -1, nullptr, s, fuse, exact);
     }
     if (sur)
         launch_volume(op, lam, dtype, mode, x, y, f, 0, s, fuse);

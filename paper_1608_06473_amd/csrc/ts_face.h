@@ -67,26 +67,80 @@ __device__ __forceinline__ int face_type(int N, int i, int j, int k) {
     return i == 0 ? 0 : j == 0 ? 1 : k == 0 ? 2 : 3;
 }
 
-template <int F, typename T>
-__device__ __forceinline__ void face_acc_a(const double* __restrict__ sw, int n2, const T* xm,
-                                           const int o[NW], double& of) {
+// element index, within its macro, of row entry e of a face node: entries
+// 0..10 through the first copy's directions (offsets oa), 11..14 through the
+// second copy's inward directions (offsets ob)
+template <int F>
+__device__ __forceinline__ void face_ix_a(const int oa[NW], int ix[NW]) {
 #pragma unroll
-    for (int e = 1; e < 11; e++) of += sw[(size_t)e * n2] * (double)xm[o[kFaceDirs.a[F][e]]];
+    for (int e = 0; e < 11; e++) ix[e] = oa[kFaceDirs.a[F][e]];
 }
-template <int F, typename T>
-__device__ __forceinline__ void face_acc_b(const double* __restrict__ sw, int n2, const T* xm,
-                                           const int o[NW], double& of) {
+template <int F>
+__device__ __forceinline__ void face_ix_b(const int ob[NW], int ix[NW]) {
 #pragma unroll
-    for (int e = 0; e < 4; e++) of += sw[(size_t)(11 + e) * n2] * (double)xm[o[kFaceDirs.b[F][e]]];
+    for (int e = 0; e < 4; e++) ix[11 + e] = ob[kFaceDirs.b[F][e]];
+}
+
+template <int FQ>
+struct FaceBasis {
+    static constexpr int M2 = (FQ + 1) * (FQ + 2) / 2;
+};
+
+// monomial c of the face basis at (u, v): exponents (d - l, l) for the c-th
+// pair in the order (d, l) = (0,0), (1,0), (1,1), (2,0), ...
+template <int C>
+struct FaceExp {
+    static constexpr int d() {
+        int dd = 0, c = C;
+        while (c > dd) {
+            c -= dd + 1;
+            dd++;
+        }
+        return dd;
+    }
+    static constexpr int l() {
+        int dd = 0, c = C;
+        while (c > dd) {
+            c -= dd + 1;
+            dd++;
+        }
+        return c;
+    }
+};
+
+__device__ __forceinline__ double ipow_c(double x, int n) {
+    double r = 1.0;
+    for (int a = 0; a < n; a++) r *= x;
+    return r;
+}
+
+template <int FQ, int C = 0>
+__device__ __forceinline__ void face_phi(double u, double v, double* phi) {
+    if constexpr (C < FaceBasis<FQ>::M2) {
+        constexpr int d = FaceExp<C>::d(), l = FaceExp<C>::l();
+        phi[C] = ipow_c(u, d - l) * ipow_c(v, l);
+        face_phi<FQ, C + 1>(u, v, phi);
+    }
+}
+
+// the face basis at the first copy (i, j, k) on face type fa
+template <int FQ>
+__device__ __forceinline__ void face_basis(int N, int fa, int i, int j, int k,
+                                           double phi[FaceBasis<FQ>::M2]) {
+    const double invN = 1.0 / (double)N;
+    const double u = (double)(fa == 0 ? j : i) * invN - 1.0 / 3.0;
+    const double v = (double)(fa <= 1 ? k : j) * invN - 1.0 / 3.0;
+    face_phi<FQ>(u, v, phi);
 }
 
 // One face fast-path node t (position q = list ? list[t] : t); same modes as
-// k_iface.
-template <typename T, int MODE>
+// k_iface.  FQ = 0: the stored exact row; FQ > 0: the face fit of degree FQ.
+template <typename T, int MODE, int FQ = 0>
 __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restrict__ y,
                                            const T* __restrict__ f,
                                            const int4* __restrict__ cp,
-                                           const double* __restrict__ sten, int n2,
+                                           const double* __restrict__ sten,
+                                           const double* __restrict__ fcoef, int n2,
                                            const int* __restrict__ list, int t, int N, int64_t B,
                                            double* __restrict__ tmp) {
     const int q = list ? list[t] : t;
@@ -94,24 +148,77 @@ __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restric
     const int ba = (int)bidx(N, ca.y, ca.z, ca.w), bb = (int)bidx(N, cb.y, cb.z, cb.w);
     const T* xa = x + (size_t)ca.x * B;
     const T* xb = x + (size_t)cb.x * B;
-    const double* sw = sten + q;
-    int o[NW];
-    double of = 0.0;
-    nbr_index(ba, N + 1 - ca.w, ca.z, o);
-    switch (face_type(N, ca.y, ca.z, ca.w)) {
-        case 0: face_acc_a<0>(sw, n2, xa, o, of); break;
-        case 1: face_acc_a<1>(sw, n2, xa, o, of); break;
-        case 2: face_acc_a<2>(sw, n2, xa, o, of); break;
-        default: face_acc_a<3>(sw, n2, xa, o, of); break;
+    const int fa = face_type(N, ca.y, ca.z, ca.w);
+    int ix[NW];
+    {
+        int o[NW];
+        nbr_index(ba, N + 1 - ca.w, ca.z, o);
+        switch (fa) {
+            case 0: face_ix_a<0>(o, ix); break;
+            case 1: face_ix_a<1>(o, ix); break;
+            case 2: face_ix_a<2>(o, ix); break;
+            default: face_ix_a<3>(o, ix); break;
+        }
+        nbr_index(bb, N + 1 - cb.w, cb.z, o);
+        switch (face_type(N, cb.y, cb.z, cb.w)) {
+            case 0: face_ix_b<0>(o, ix); break;
+            case 1: face_ix_b<1>(o, ix); break;
+            case 2: face_ix_b<2>(o, ix); break;
+            default: face_ix_b<3>(o, ix); break;
+        }
     }
-    nbr_index(bb, N + 1 - cb.w, cb.z, o);
-    switch (face_type(N, cb.y, cb.z, cb.w)) {
-        case 0: face_acc_b<0>(sw, n2, xb, o, of); break;
-        case 1: face_acc_b<1>(sw, n2, xb, o, of); break;
-        case 2: face_acc_b<2>(sw, n2, xb, o, of); break;
-        default: face_acc_b<3>(sw, n2, xb, o, of); break;
+    // entry e: its weight (stored row, or the face fit at this node) times x
+    // at its neighbour; the fitted weights are formed one at a time
+    double of = 0.0, dg;
+    if constexpr (FQ == 0) {
+        const double* sw = sten + q;
+        dg = sw[0];
+#pragma unroll
+        for (int e = 1; e < NW; e++)
+            of += sw[(size_t)e * n2] * (double)(e < 11 ? xa : xb)[ix[e]];
+    } else {
+        constexpr int M2 = FaceBasis<FQ>::M2;
+        double phi[M2];
+        face_basis<FQ>(N, fa, ca.y, ca.z, ca.w, phi);
+        const int blk = ca.x * 4 + fa;
+        // Almost every wavefront lies on one face: then the coefficient block
+        // is wave-uniform and is read through the scalar cache; wavefronts
+        // across two faces read it per lane.
+        const int b0 = __builtin_amdgcn_readfirstlane(blk);
+        if (__builtin_amdgcn_ballot_w64(blk != b0) == 0) {
+            const double* cf = fcoef + (size_t)b0 * (NW * M2);
+            dg = 0.0;
+#pragma unroll
+            for (int c = 0; c < M2; c++) dg += cf[c] * phi[c];
+#pragma unroll
+            for (int e = 1; e < NW; e++) {
+                double we = 0.0;
+#pragma unroll
+                for (int c = 0; c < M2; c++) we += cf[e * M2 + c] * phi[c];
+                of += we * (double)(e < 11 ? xa : xb)[ix[e]];
+                if (e % 2 == 0) asm volatile("" : "+s"(cf) : "v"(of));
+            }
+        } else {
+            const double* cf = fcoef + (size_t)blk * (NW * M2);
+            dg = 0.0;
+#pragma unroll
+            for (int c = 0; c < M2; c++) dg += cf[c] * phi[c];
+#pragma unroll
+            for (int e = 1; e < NW; e++) {
+                double we = 0.0;
+#pragma unroll
+                for (int c = 0; c < M2; c++) we += cf[e * M2 + c] * phi[c];
+                of += we * (double)(e < 11 ? xa : xb)[ix[e]];
+                // One entry's coefficients in flight: the face rows share the
+                // register budget of the fused volume kernel.  The empty asm
+                // takes this entry's weight and hands back the coefficient
+                // pointer, so the next entry's loads cannot be issued before
+                // the weight is formed (the gathers of x stay free to run
+                // ahead).
+                asm volatile("" : "+v"(cf) : "v"(of));
+            }
+        }
     }
-    const double dg = sw[0];
     const size_t sa = (size_t)ca.x * B + ba, sb = (size_t)cb.x * B + bb;
     if (MODE == 2) {
         tmp[t] = ((double)f[sa] - of) / dg;

@@ -144,6 +144,11 @@ struct Level {
     // f2g_off[p] .. f2g_off[p] + n_f2_phase[p]
     DBuf<int4> f2g_cp;
     DBuf<double> f2g_sten;
+    // face fast path grouped by face: nodes f2_face_off[f] .. f2_face_off[f+1]
+    // of the canonical copy belong to the f-th interior face, in the face
+    // frame order (b = 1 .. N-2, a = 1 .. N-1-b)
+    DBuf<int> f2_face_off;
+    int n_f2_faces = 0;
     int f2g_off[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
     int n_f2_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
     // per GS phase: node ids of the general lists
@@ -211,6 +216,10 @@ struct LevelOp {
     int n_sur = 0, n_ifem = 0;
     bool has_coef = false;
     DBuf<double> gs_tmp;   // interface Gauss-Seidel values of one phase
+    // surrogate rows of interior faces: [nt][4][15][m2] by (first macro of
+    // the face, its face type); face_fit: used on this level
+    DBuf<double> fcoef;
+    bool face_fit = false;
 };
 
 }  // namespace ts
@@ -243,8 +252,14 @@ namespace ts {
 // float vectors).
 void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                    const void* f, int colour, hipStream_t s, bool fuse_face = false);
+// exact: the face rows take the stored exact stencils even where the
+// operator has face fits (exact residuals)
 void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
-                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face = false);
+                  const void* f, int phase, double* tmp, hipStream_t s, bool skip_face = false,
+                  bool exact = false);
+// least-squares fits of the face rows of a level (one workgroup per interior
+// face) into fcoef [nt][4][15][m2]; the exact face rows must exist
+void launch_face_fit(const Level& L, int q, int jsamp, int nt, double* fcoef, hipStream_t s);
 void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
                           void* u, hipStream_t s);
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,

@@ -280,7 +280,11 @@ __device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g, T r
 
 // WP: weight provider (SurrogateW or SurrogateHalfW), T: vector type, W:
 // weight arithmetic type (float for the FP16 provider's products).
-template <class WP, typename T, typename W, int MODE, int R, int KPT>
+// Minimum wavefronts per SIMD the compiler is held to (register budget):
+// the apply and residual at q <= 2 with narrow staging; no bound otherwise.
+// FF: the fused face rows take the face fits (degree kQ) instead of the
+// stored exact rows
+template <class WP, typename T, typename W, int MODE, int R, int KPT, bool FF = false>
 __global__ __launch_bounds__(VOL_THREADS)
 __attribute__((amdgpu_waves_per_eu(MODE != 2 && WP::kQ <= 2 && KPT <= 2 ? TS_VOL_WAVES_EU : 1)))
 void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restrict__ coef_f,
@@ -288,7 +292,8 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
                 const int* __restrict__ stage, int N, int64_t B, int colour,
                 const int4* __restrict__ f2cp = nullptr,
-                const double* __restrict__ f2sten = nullptr, int n2 = 0) {
+                const double* __restrict__ f2sten = nullptr,
+                const double* __restrict__ f2coef = nullptr, int n2 = 0) {
     // the residual's f ring needs registers: shorter staging prefetch there
     // when the kernel is compiled for three waves
     constexpr int PF = MODE == 1 && WP::kQ <= 2 && KPT <= 2 ? 2 : TS_VOL_PF;
@@ -300,7 +305,9 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
         const int xcd = bx & 7, loc = bx >> 3, grp = loc / 3, r3 = loc - 3 * grp;
         if (r3 == 2) {
             const int t = (grp * 8 + xcd) * VOL_THREADS + (int)threadIdx.x;
-            if (t < n2) face2_node<T, MODE>(x, y, f, f2cp, f2sten, n2, nullptr, t, N, B, nullptr);
+            if (t < n2)
+                face2_node<T, MODE, FF ? WP::kQ : 0>(x, y, f, f2cp, f2sten, f2coef, n2, nullptr,
+                                                     t, N, B, nullptr);
             return;
         }
         bx = ((grp * 2 + r3) << 3) | xcd;

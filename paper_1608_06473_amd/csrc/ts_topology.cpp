@@ -231,14 +231,21 @@ Level& Mesh::level(int lam) {
     {
         std::vector<int> f2, rest;
         std::vector<int4> c0, c1, rcc;
-        std::vector<int> f2pos(n_if, -1), rcb(n_if, -1);
+        std::vector<int> f2pos(n_if, -1), rcb(n_if, -1), f2f;
         std::vector<int64_t> dslots;
+        const int64_t nfi = (int64_t)(N - 1) * (N - 2) / 2;  // free nodes per face
+        int64_t last_face = -1;
         for (int64_t n = 0; n < n_if; n++) {
             const bool face = n >= nv + ne * (N - 1);
             if (flag[n] & 1) {
                 for (int c = off[n]; c < off[n + 1]; c++)
                     dslots.push_back((int64_t)cp[c].x * L->B + bidx(N, cp[c].y, cp[c].z, cp[c].w));
             } else if (face && off[n + 1] - off[n] == 2) {
+                const int64_t fi = (n - (nv + ne * (N - 1))) / nfi;
+                if (fi != last_face) {
+                    f2f.push_back((int)f2.size());
+                    last_face = fi;
+                }
                 f2pos[n] = (int)f2.size();
                 f2.push_back((int)n);
                 c0.push_back(cp[off[n]]);
@@ -257,6 +264,11 @@ Level& Mesh::level(int lam) {
         std::vector<int4> c01(c0);
         c01.insert(c01.end(), c1.begin(), c1.end());
         L->n_f2 = (int)f2.size();
+        f2f.push_back(L->n_f2);
+        for (size_t g = 0; g + 1 < f2f.size(); g++)
+            if (f2f[g + 1] - f2f[g] != nfi) throw Error{TS_EINVAL, "interior face with missing nodes"};
+        L->n_f2_faces = (int)f2f.size() - 1;
+        L->f2_face_off.upload(f2f);
         L->f2_node.upload(f2);
         L->f2_cp.upload(c01);
         L->n_rest = (int)rest.size();

@@ -147,6 +147,25 @@ const char *ts_last_error(void);
 int ts_mesh_create(const double *vtx, int64_t nv, const int64_t *tet, int64_t nt, int geom,
                    ts_mesh **out);
 int ts_mesh_destroy(ts_mesh *mesh);
+/* A mesh with the connectivity of `like` and its own vertex coordinates (vtx:
+ * nv x 3 host doubles, copied).  The levels already built on `like` (index
+ * lists, tiles, lane orders: everything that depends on the connectivity
+ * only) are shared, not rebuilt; everything that depends on the coordinates
+ * is the new mesh's own (Sec. 2.2: the blending map depends on the vertices
+ * only).  Levels built later are built per mesh.  `like` may be destroyed
+ * before the new mesh.  Building levels on `like` while this call runs is
+ * not allowed.  TS_EINVAL if a macro is degenerate. */
+int ts_mesh_create_like(const ts_mesh *like, const double *vtx, ts_mesh **out);
+/* Replace the vertex coordinates (vtx: nv x 3 host doubles, copied) of a mesh
+ * and keep its connectivity and every level built on it (interface lists,
+ * tiles, lane orders), so that a caller solving many problems on one macro
+ * layout with different radii builds the levels once (Sec. 2.2: the blending
+ * map depends on the vertices only).  Stored coordinates and stored interface
+ * stencils are recomputed on next use.  Fails with TS_EINVAL while an
+ * operator created on the mesh is alive (its coefficients describe the old
+ * geometry) or if a macro becomes degenerate (the mesh is then unchanged);
+ * no work that reads the mesh may be in flight. */
+int ts_mesh_set_vertices(ts_mesh *mesh, const double *vtx);
 int ts_layout(ts_mesh *mesh, int level, ts_layout_info *out);
 
 /* canonical <-> block conversions of float64 device vectors.  to_block zeroes

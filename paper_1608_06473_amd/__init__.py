@@ -65,6 +65,8 @@ _SIGS = {
     "ts_last_error": (C.c_char_p, []),
     "ts_mesh_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     "ts_mesh_destroy": (C.c_int, [C.c_void_p]),
+    "ts_mesh_set_vertices": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ts_mesh_create_like": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_layout": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "ts_canon_to_block": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_block_to_canon": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -157,6 +159,18 @@ def ts_mesh_create(vtx, tet, geom=TS_GEOM_SHELL):
 
 def ts_mesh_destroy(h):
     return _check(lib().ts_mesh_destroy(h))
+
+
+def ts_mesh_create_like(like, vtx):
+    v = np.ascontiguousarray(vtx, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().ts_mesh_create_like(like, v.ctypes.data_as(C.c_void_p), C.byref(h)))
+    return h
+
+
+def ts_mesh_set_vertices(h, vtx):
+    v = np.ascontiguousarray(vtx, dtype=np.float64)
+    return _check(lib().ts_mesh_set_vertices(h, v.ctypes.data_as(C.c_void_p)))
 
 
 def ts_layout(mesh, level):
@@ -301,13 +315,30 @@ def dtype_torch(dt):
 class Mesh:
     """Owning wrapper of a ts_mesh handle."""
 
-    def __init__(self, vtx, tet, geom=TS_GEOM_SHELL):
+    def __init__(self, vtx, tet, geom=TS_GEOM_SHELL, like=None):
+        """like: a Mesh with the same connectivity whose built levels are
+        shared (ts_mesh_create_like); tet and geom are then its own."""
         self.vtx = np.ascontiguousarray(vtx, dtype=np.float64)
-        self.tet = np.ascontiguousarray(tet, dtype=np.int64)
-        self.h = ts_mesh_create(self.vtx, self.tet, geom)
+        if like is not None:
+            if self.vtx.shape != like.vtx.shape:
+                raise ValueError("vertex array of a different shape")
+            self.tet = like.tet
+            self.h = ts_mesh_create_like(like.h, self.vtx)
+        else:
+            self.tet = np.ascontiguousarray(tet, dtype=np.int64)
+            self.h = ts_mesh_create(self.vtx, self.tet, geom)
 
     def layout(self, level):
         return ts_layout(self.h, level)
+
+    def set_vertices(self, vtx):
+        """New vertex coordinates, same connectivity; the levels built so far
+        are kept (no operator on this mesh may be alive)."""
+        v = np.ascontiguousarray(vtx, dtype=np.float64)
+        if v.shape != self.vtx.shape:
+            raise ValueError("vertex array of a different shape")
+        ts_mesh_set_vertices(self.h, v)
+        self.vtx = v
 
     def zeros(self, level, dt=TS_F64):
         import torch

@@ -773,28 +773,27 @@ void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s) {
 constexpr int GJB = 64;
 
 // D = A[K,K]^-1 by unblocked Gauss-Jordan in LDS (one workgroup)
-__global__ __launch_bounds__(256) void k_bgj_diag(const double* __restrict__ A, int n, int k0,
-                                                  int b, double* __restrict__ D) {
+__global__ __launch_bounds__(64) void k_bgj_diag(const double* __restrict__ A, int n, int k0,
+                                                 int b, double* __restrict__ D) {
+    // one wavefront; lane j owns column j of the block during the elimination
     __shared__ double M[GJB][GJB + 1];
     __shared__ double col[GJB];
-    for (int e = threadIdx.x; e < b * b; e += 256) M[e / b][e % b] = A[(size_t)(k0 + e / b) * n + k0 + e % b];
+    const int j = (int)threadIdx.x;
+    for (int i = 0; i < b; i++) M[i][j] = j < b ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
     __syncthreads();
     for (int k = 0; k < b; k++) {
         const double piv = M[k][k];
-        if (threadIdx.x < b) col[threadIdx.x] = M[threadIdx.x][k];
+        if (j < b) col[j] = M[j][k];
         __syncthreads();
-        if (threadIdx.x < b) {
-            const int j = threadIdx.x;
-            M[k][j] = (j == k) ? 1.0 / piv : M[k][j] / piv;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < b * b; e += 256) {
-            const int i = e / b, j = e % b;
-            if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - col[i] * M[k][j];
+        if (j < b) {
+            const double nk = (j == k) ? 1.0 / piv : M[k][j] / piv;
+            M[k][j] = nk;
+            for (int i = 0; i < b; i++)
+                if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - col[i] * nk;
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < b * b; e += 256) D[e] = M[e / b][e % b];
+    for (int e = j; e < b * b; e += 64) D[e] = M[e / b][e % b];
 }
 
 // P[r][j] = sum_s D[r][s] A[k0+s][j] for every column j (b x n)
@@ -850,19 +849,21 @@ __global__ __launch_bounds__(256) void k_bgj_update(double* __restrict__ A, int 
     }
 }
 
-// A[i][K] = -A[i][K] D for rows outside K; then the pivot rows and block
+// A[i][K] = -A[i][K] D for rows outside K (four rows per workgroup, one
+// column per lane); then the pivot rows and block
 __global__ __launch_bounds__(256) void k_bgj_cols(double* __restrict__ A, int n, int k0, int b,
                                                   const double* __restrict__ D) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n || (i >= k0 && i < k0 + b)) return;
-    double row[GJB];
-#pragma unroll
-    for (int q = 0; q < GJB; q++) row[q] = q < b ? A[(size_t)i * n + k0 + q] : 0.0;
-    for (int c = 0; c < b; c++) {
+    __shared__ double Ds[GJB][GJB + 1];
+    __shared__ double R[4][GJB];
+    const int c = (int)threadIdx.x & 63, rr = (int)threadIdx.x >> 6;
+    const int i = (int)blockIdx.x * 4 + rr;
+    for (int e = (int)threadIdx.x; e < b * b; e += 256) Ds[e / b][e % b] = D[e];
+    const bool act = i < n && !(i >= k0 && i < k0 + b) && c < b;
+    if (act) R[rr][c] = A[(size_t)i * n + k0 + c];
+    __syncthreads();
+    if (act) {
         double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < GJB; q++)
-            if (q < b) v += row[q] * D[q * b + c];
+        for (int q = 0; q < b; q++) v += R[rr][q] * Ds[q][c];
         A[(size_t)i * n + k0 + c] = -v;
     }
 }
@@ -882,10 +883,10 @@ void launch_gj_blocked(double* A, int n, double* work, hipStream_t s) {
     const unsigned gt = (unsigned)((n + 63) / 64), gc = (unsigned)((n + 255) / 256);
     for (int k0 = 0; k0 < n; k0 += GJB) {
         const int b = std::min(GJB, n - k0);
-        k_bgj_diag<<<1, 256, 0, s>>>(A, n, k0, b, D);
+        k_bgj_diag<<<1, 64, 0, s>>>(A, n, k0, b, D);
         k_bgj_panel<<<dim3(gc, b), 256, 0, s>>>(A, n, k0, b, D, P);
         k_bgj_update<<<dim3(gt, gt), 256, 0, s>>>(A, n, k0, b, P);
-        k_bgj_cols<<<gc, 256, 0, s>>>(A, n, k0, b, D);
+        k_bgj_cols<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(A, n, k0, b, D);
         k_bgj_rows<<<dim3(gc, b), 256, 0, s>>>(A, n, k0, b, P, D);
     }
     TS_HIP(hipGetLastError());

@@ -216,7 +216,8 @@ __global__ __launch_bounds__(256) void k_face_fit(const int4* __restrict__ cp,
         for (int c = 0; c < M2; c++) out[w * M2 + c] = X[c][w];
 }
 
-void launch_face_fit(const Level& L, int q, int jsamp, int nt, double* fcoef, hipStream_t s) {
+void launch_face_fit(const Level& L, const double* f2sten, int q, int jsamp, int nt, double* fcoef,
+                     hipStream_t s) {
     const int N = L.N;
     int l = 0;
     while ((4 << l) < N) l++;
@@ -227,7 +228,7 @@ void launch_face_fit(const Level& L, int q, int jsamp, int nt, double* fcoef, hi
     TS_HIP(hipMemsetAsync(fcoef, 0, (size_t)nt * 4 * NW * ((q + 1) * (q + 2) / 2) * sizeof(double), s));
     if (L.n_f2_faces == 0) return;
     const unsigned g = (unsigned)L.n_f2_faces;
-#define TS_FF(Q) k_face_fit<Q><<<g, 256, 0, s>>>(L.f2_cp.p, L.f2_sten.p, L.n_f2, L.f2_face_off.p, N, Ns, fcoef)
+#define TS_FF(Q) k_face_fit<Q><<<g, 256, 0, s>>>(L.f2_cp.p, f2sten, L.n_f2, L.f2_face_off.p, N, Ns, fcoef)
     switch (q) {
         case 1: TS_FF(1); break;
         case 2: TS_FF(2); break;
@@ -273,30 +274,31 @@ __global__ __launch_bounds__(128) void k_face2_stencils(const int4* __restrict__
     }
     for (int e = 0; e < 4; e++) sten[(size_t)(11 + e) * n2 + q] = sb[kFaceDirs.b[fb][e]];
 }
-// Stored stencils of a level's interface nodes (built on first use): the
-// combined row of every face fast-path node ([15][n_f2]) and the partial
-// stencil of every copy of the other free lower-primitive nodes ([15][n_rc]).
+// Stored stencils of a level's interface nodes (built on first use, and
+// again after the vertex coordinates change): the combined row of every face
+// fast-path node ([15][n_f2]) and the partial stencil of every copy of the
+// other free lower-primitive nodes ([15][n_rc]).
 const double* face_stencils(Mesh& M, int lam, hipStream_t s) {
-    Level& L = M.level(lam);
-    if (!L.f2_sten.p && L.n_f2) {
-        L.f2_sten.alloc((size_t)NW * L.n_f2);
+    const Level& L = M.level(lam);
+    LevelGeo& G = M.level_geo(lam);
+    if (G.sten_gen == M.geo_gen) return G.f2_sten.p;
+    if (L.n_f2) {
+        if (!G.f2_sten.p) G.f2_sten.alloc((size_t)NW * L.n_f2);
+        if (!G.f2g_sten.p) G.f2g_sten.alloc((size_t)NW * L.n_f2);
         k_face2_stencils<<<(L.n_f2 + 127) / 128, 128, 0, s>>>(L.f2_cp.p, L.n_f2, M.d_geom.p,
-                                                              M.d_topo.p, L.N, L.f2_sten.p);
-        TS_HIP(hipGetLastError());
-    }
-    if (!L.f2g_sten.p && L.n_f2) {
-        L.f2g_sten.alloc((size_t)NW * L.n_f2);
+                                                              M.d_topo.p, L.N, G.f2_sten.p);
         k_face2_stencils<<<(L.n_f2 + 127) / 128, 128, 0, s>>>(L.f2g_cp.p, L.n_f2, M.d_geom.p,
-                                                              M.d_topo.p, L.N, L.f2g_sten.p);
+                                                              M.d_topo.p, L.N, G.f2g_sten.p);
         TS_HIP(hipGetLastError());
     }
-    if (!L.rest_sten.p && L.n_rc) {
-        L.rest_sten.alloc((size_t)NW * L.n_rc);
+    if (L.n_rc) {
+        if (!G.rest_sten.p) G.rest_sten.alloc((size_t)NW * L.n_rc);
         k_copy_stencils<<<(L.n_rc + 127) / 128, 128, 0, s>>>(L.rc_cp.p, L.n_rc, M.d_geom.p, L.N,
-                                                             L.rest_sten.p);
+                                                             G.rest_sten.p);
         TS_HIP(hipGetLastError());
     }
-    return L.f2_sten.p;
+    G.sten_gen = M.geo_gen;
+    return G.f2_sten.p;
 }
 
 template <typename T>
@@ -384,12 +386,14 @@ void launch_ifem_k4(const Level& L, const double* xyz, int nt, const int* mlist,
 
 // blended coordinates of every slot of a level, computed on first use
 static const double* level_coords(Mesh& M, int lam, hipStream_t s) {
-    Level& L = M.level(lam);
-    if (!L.xyz.p) {
-        L.xyz.alloc((size_t)3 * L.len);
-        launch_coords(M, lam, L.xyz.p, s);
+    const Level& L = M.level(lam);
+    LevelGeo& G = M.level_geo(lam);
+    if (G.xyz_gen != M.geo_gen) {
+        if (!G.xyz.p) G.xyz.alloc((size_t)3 * L.len);
+        launch_coords(M, lam, G.xyz.p, s);
+        G.xyz_gen = M.geo_gen;
     }
-    return L.xyz.p;
+    return G.xyz.p;
 }
 
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
@@ -424,7 +428,8 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     // range of the phase-grouped copy
     const int go = phase >= 0 ? L.f2g_off[phase] : 0;
     const int4* cp2 = phase >= 0 ? L.f2g_cp.p + go : L.f2_cp.p;
-    const double* sten = phase >= 0 ? L.f2g_sten.p + go : L.f2_sten.p;
+    const LevelGeo& G = M.level_geo(lam);
+    const double* sten = phase >= 0 ? G.f2g_sten.p + go : G.f2_sten.p;
     const int n2 = skip_face ? 0 : phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
@@ -446,7 +451,7 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
 #define TS_IF(T_, M_)                                                                         \
     k_iface<T_, M_><<<(nr + 3) / 4, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,           \
                                                      L.if_off.p, L.if_copy.p, L.rc_base.p,    \
-                                                     L.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
+                                                     G.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
                                                      tmp_r)
     if (n2) {
         if (dtype == TS_F64) {

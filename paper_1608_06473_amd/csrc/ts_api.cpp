@@ -97,10 +97,10 @@ static void split_macros(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
 static void setup_face_fit(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
     Mesh& M = op->mesh->m;
     const Level& L = M.level(lam);
-    face_stencils(M, lam, s);
+    const double* f2sten = face_stencils(M, lam, s);
     const int m2 = (op->p.q + 1) * (op->p.q + 2) / 2;
     lo.fcoef.alloc((size_t)M.nt * 4 * NW * m2);
-    launch_face_fit(L, op->p.q, op->p.sample_j, (int)M.nt, lo.fcoef.p, s);
+    launch_face_fit(L, f2sten, op->p.q, op->p.sample_j, (int)M.nt, lo.fcoef.p, s);
     TS_HIP(hipStreamSynchronize(s));
 }
 
@@ -387,6 +387,54 @@ int ts_mesh_destroy(ts_mesh* mesh) {
     return guarded([&] { delete mesh; });
 }
 
+int ts_mesh_create_like(const ts_mesh* like, const double* vtx, ts_mesh** out) {
+    return guarded([&] {
+        TS_REQUIRE(like && vtx && out, TS_EINVAL, "null argument");
+        const Mesh& A = like->m;
+        auto* m = new ts_mesh();
+        try {
+            Mesh& M = m->m;
+            M.nv = A.nv; M.nt = A.nt; M.ne = A.ne; M.nf = A.nf;
+            M.geom = A.geom;
+            M.vtx.assign(vtx, vtx + 3 * A.nv);
+            M.tet = A.tet;
+            M.edges = A.edges;
+            M.faces = A.faces;
+            M.vdir = A.vdir; M.edir = A.edir; M.fdir = A.fdir;
+            M.v_tets = A.v_tets; M.e_tets = A.e_tets; M.f_tets = A.f_tets;
+            M.topo = A.topo;
+            M.device = A.device;
+            M.d_topo.alloc(M.topo.size());
+            TS_HIP(hipMemcpy(M.d_topo.p, A.d_topo.p, M.topo.size() * sizeof(MacroTopo),
+                             hipMemcpyDeviceToDevice));
+            build_geometry(M);
+            M.levels = A.levels;  // connectivity-only level data, shared
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+int ts_mesh_set_vertices(ts_mesh* mesh, const double* vtx) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && vtx, TS_EINVAL, "null argument");
+        TS_REQUIRE(mesh->ops.load() == 0, TS_EINVAL,
+                   "operators created on this mesh must be destroyed first");
+        Mesh& M = mesh->m;
+        std::vector<double> old(M.vtx);
+        M.vtx.assign(vtx, vtx + 3 * M.nv);
+        try {
+            build_geometry(M);
+        } catch (...) {
+            M.vtx.swap(old);
+            throw;
+        }
+        M.geo_gen++;  // stored coordinates and interface stencils are rebuilt on use
+    });
+}
+
 int ts_layout(ts_mesh* mesh, int level, ts_layout_info* out) {
     return guarded([&] {
         TS_REQUIRE(mesh && out, TS_EINVAL, "null argument");
@@ -469,12 +517,14 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             delete op;
             throw;
         }
+        mesh->ops++;
         *out = op;
     });
 }
 
 int ts_op_destroy(ts_op* op) {
     return guarded([&] {
+        if (op && op->mesh) op->mesh->ops--;
         delete op;
     });
 }

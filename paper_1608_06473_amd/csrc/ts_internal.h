@@ -93,6 +93,8 @@ struct MacroTopo {
 constexpr int N_IF_PHASES = 6;
 
 // Per-level layout and interface maps.
+// Level data that depend only on the connectivity: index lists, tiles, lane
+// orders.  Meshes with the same connectivity may share them.
 struct Level {
     int lam = 0, N = 0;
     int64_t B = 0, len = 0;       // block size, vector length (n_macros * B)
@@ -117,8 +119,6 @@ struct Level {
     DBuf<unsigned> ap_lanes;      // per tile and lane: i | j << 16 (apply order)
     DBuf<int> stage_tbl;          // per tile and staged plane k0-1+st (st = 0..R+1):
                                   // first block element of rows j0-1 .. j1 (0 if none)
-    DBuf<double> xyz;             // blended coordinates of every slot (x, y, z),
-                                  // built on the first element-wise volume pass
     // fast path for free nodes of interior faces (exactly two copies): node
     // ids, both copies, and their combined rows as struct of arrays
     // [slot][face node] so that lane loads are coalesced; the remaining free
@@ -127,14 +127,12 @@ struct Level {
     int n_f2 = 0;
     DBuf<int> f2_node;
     DBuf<int4> f2_cp;             // [2][n_f2]
-    DBuf<double> f2_sten;         // combined rows [15][n_f2]
     DBuf<int> rest;               // other free lower-primitive nodes (node ids)
     int n_rest = 0;
     // stored partial stencils of the copies of the `rest` nodes: copy c of
     // node n has compact index rc_base[n] + (c - off[n]); [15][n_rc]
     DBuf<int> rc_base;
     DBuf<int4> rc_cp;
-    DBuf<double> rest_sten;
     int n_rc = 0;
     // block slots of every copy of every Dirichlet node (zero rows)
     DBuf<int64_t> dir_slots;
@@ -143,7 +141,6 @@ struct Level {
     // [2][n_f2] and combined rows [15][n_f2]; phase p is the range
     // f2g_off[p] .. f2g_off[p] + n_f2_phase[p]
     DBuf<int4> f2g_cp;
-    DBuf<double> f2g_sten;
     // face fast path grouped by face: nodes f2_face_off[f] .. f2_face_off[f+1]
     // of the canonical copy belong to the f-th interior face, in the face
     // frame order (b = 1 .. N-2, a = 1 .. N-1-b)
@@ -178,6 +175,18 @@ struct Level {
 constexpr int VOL_R = TS_VOL_R;  // planes per volume tile
 constexpr int VOL_THREADS = 256;
 
+// Level data that depend on the vertex coordinates, owned by each mesh and
+// built on first use: the blended coordinates of every slot (element-wise
+// volume rows), the combined rows of the face fast path in canonical and
+// phase-grouped order ([15][n_f2] each), the partial stencils of the other
+// interface copies ([15][n_rc]); gens: the geometry generation they were
+// computed for (-1: none).
+struct LevelGeo {
+    int xyz_gen = -1, sten_gen = -1;
+    DBuf<double> xyz;
+    DBuf<double> f2_sten, f2g_sten, rest_sten;
+};
+
 struct Mesh {
     int64_t nv = 0, nt = 0, ne = 0, nf = 0;
     int geom = TS_GEOM_SHELL;
@@ -191,9 +200,16 @@ struct Mesh {
     std::vector<MacroGeom> geomh;
     DBuf<MacroGeom> d_geom;
     DBuf<MacroTopo> d_topo;
-    std::map<int, std::unique_ptr<Level>> levels;
+    std::map<int, std::shared_ptr<Level>> levels;
+    std::map<int, std::unique_ptr<LevelGeo>> geo;
     int device = 0;
+    int geo_gen = 0;  // bumped whenever the vertex coordinates change
 
+    LevelGeo& level_geo(int lam) {
+        auto& g = geo[lam];
+        if (!g) g = std::make_unique<LevelGeo>();
+        return *g;
+    }
     Level& level(int lam);
     int64_t num_unique(int N) const {
         return nv + ne * (N - 1) + nf * (int64_t)(N - 1) * (N - 2) / 2 +
@@ -202,6 +218,8 @@ struct Mesh {
 };
 
 void build_topology(Mesh& M);
+// macro geometry records (host and device) from the vertex coordinates
+void build_geometry(Mesh& M);
 const double* face_stencils(Mesh& M, int lam, hipStream_t s);
 
 // ------------------------------------------------------------ operators
@@ -226,6 +244,7 @@ struct LevelOp {
 
 struct ts_mesh {
     ts::Mesh m;
+    std::atomic<int> ops{0};  // operators created on this mesh and not destroyed
 };
 
 struct ts_op {
@@ -259,7 +278,8 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
                   bool exact = false);
 // least-squares fits of the face rows of a level (one workgroup per interior
 // face) into fcoef [nt][4][15][m2]; the exact face rows must exist
-void launch_face_fit(const Level& L, int q, int jsamp, int nt, double* fcoef, hipStream_t s);
+void launch_face_fit(const Level& L, const double* f2sten, int q, int jsamp, int nt, double* fcoef,
+                     hipStream_t s);
 void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
                           void* u, hipStream_t s);
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,

@@ -101,8 +101,7 @@ void build_topology(Mesh& M) {
         M.edir[find_sorted(E, {k[0], k[2]})] = 1;
         M.edir[find_sorted(E, {k[1], k[2]})] = 1;
     }
-    // per-macro flags, multiplicities and geometry
-    M.geomh.assign(nt, MacroGeom{});
+    // per-macro flags and multiplicities
     for (int64_t t = 0; t < nt; t++) {
         MacroTopo& T = M.topo[t];
         for (int a = 0; a < 4; a++) T.vdir[a] = M.vdir[T.vg[a]];
@@ -114,7 +113,16 @@ void build_topology(Mesh& M) {
             T.fdir[o] = M.fdir[T.f[o]];
             T.fmult[o] = (unsigned char)M.f_tets[T.f[o]].size();
         }
-        MacroGeom& G = M.geomh[t];
+    }
+    M.d_topo.upload(M.topo);
+    build_geometry(M);
+}
+
+void build_geometry(Mesh& M) {
+    const int64_t nt = M.nt;
+    std::vector<MacroGeom> gh(nt, MacroGeom{});
+    for (int64_t t = 0; t < nt; t++) {
+        MacroGeom& G = gh[t];
         const int64_t* g = &M.tet[4 * t];
         for (int a = 0; a < 4; a++) {
             double r2 = 0;
@@ -138,15 +146,19 @@ void build_topology(Mesh& M) {
                      e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
         TS_REQUIRE(fabs(det) > 1e-300, TS_EINVAL, "degenerate macro tetrahedron");
     }
-    M.d_geom.upload(M.geomh);
-    M.d_topo.upload(M.topo);
+    M.geomh.swap(gh);
+    if (M.d_geom.p && M.d_geom.n == M.geomh.size())
+        TS_HIP(hipMemcpy(M.d_geom.p, M.geomh.data(), M.geomh.size() * sizeof(MacroGeom),
+                         hipMemcpyHostToDevice));
+    else
+        M.d_geom.upload(M.geomh);
 }
 
 Level& Mesh::level(int lam) {
     auto it = levels.find(lam);
     if (it != levels.end()) return *it->second;
     TS_REQUIRE(lam >= 2 && lam <= 9, TS_EINVAL, "level must be in 2..9");
-    auto L = std::make_unique<Level>();
+    auto L = std::make_shared<Level>();
     const int N = 1 << lam;
     L->lam = lam;
     L->N = N;

@@ -5,11 +5,20 @@ right-hand side of Gaussian bumps.  A request is admitted when it fits the
 HBM budget and a slot is free.  A worker thread then builds its mesh,
 surrogate operator and multigrid solver on the request's own stream, and
 enqueues the start of the solve (ts_solve_begin).  The scheduler thread polls
-every active solve without blocking (ts_solve_query) and, level by level,
-enqueues the next refinement iteration (ts_solve_step) of each request whose
-last one has finished.  Work of many requests is therefore in flight on the
+every active solve without blocking (ts_solve_query) and enqueues the next
+refinement iteration (ts_solve_step) of requests whose last one has finished,
+smallest level first and, within a level, in arrival order, as long as the
+work in flight stays under a budget (an iteration at level l counts
+8^(l - 7), so about two level-7 iterations run at once while small requests
+pass them).  Work of many requests is therefore in flight on the
 device at once, and requests arriving meanwhile join as slots and memory free
 up.  A request retires when its FP64 relative residual reaches the tolerance.
+
+Requests on one macro layout differ only in their radii, so the server
+keeps a template mesh of the layout whose levels (index lists, tiles, lane
+orders) are built once, on first need, and every request's mesh shares them
+(ts_mesh_create_like) with its own vertices; only the geometry-dependent data
+are built per request.
 
 Every request runs the same sequence of kernels on its own data whatever else
 is in flight (no atomics, fixed reduction order), so a result is bitwise the
@@ -19,6 +28,7 @@ from __future__ import annotations
 
 import collections
 import concurrent.futures as cf
+import threading
 import time
 
 import numpy as np
@@ -50,6 +60,8 @@ def request_bytes(n_macros, level, precision=TS_F32):
     return int(b + 32 * 2 ** 20)
 
 
+
+
 class Request:
     __slots__ = ("id", "t", "level", "r_in", "bytes", "t_admit", "t_ready", "t_done", "stream",
                  "mesh", "op", "sv", "f", "u", "info", "status", "cycles", "rel", "u_host",
@@ -75,12 +87,16 @@ class Server:
     per-macro IFEM fallback tolerance; precision: TS_F32 (FP32 V-cycles with
     FP64 refinement), TS_F16W or TS_F64; rtol: FP64 relative residual to
     reach; hbm_budget: bytes the admitted requests may use (estimate);
-    max_active: slots; keep: ids whose solutions are copied to the host.
+    max_active: slots; keep: ids whose solutions are copied to the host;
+    inflight_work: budget of refinement iterations in flight, in level-7
+    iterations (8^(level - 7) each); one iteration is always allowed;
+    warm_levels: levels whose layout data are built at start-up (else on the
+    first request that needs them).
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
                  hbm_budget=64 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
-                 keep=(), gc_batch=8):
+                 keep=(), gc_batch=8, inflight_work=2.0, warm_levels=()):
         import torch
         self.torch = torch
         self.topology = topology
@@ -92,6 +108,18 @@ class Server:
         self.fallback_tol = fallback_tol
         self.keep = set(keep)
         self.gc_batch = gc_batch
+        self.inflight_work = inflight_work
+        self.template = None  # the layout's mesh; its levels are shared
+        self.built = set()
+        if warm_levels:
+            vtx, tet = TOPOLOGIES[topology](0.55)
+            self.template = Mesh(vtx, tet)
+            for lam in range(2, max(warm_levels) + 1):
+                self.template.layout(lam)
+                self.built.add(lam)
+        self.tlock = threading.Lock()
+        self.shared = 0       # requests whose levels were all built already
+        self.setup_workers = setup_workers
         self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
 
     # -- per request ---------------------------------------------------------
@@ -99,7 +127,16 @@ class Server:
         torch = self.torch
         r.stream = torch.cuda.Stream()
         vtx, tet = TOPOLOGIES[self.topology](r.r_in)
-        r.mesh = Mesh(vtx, tet)
+        with self.tlock:  # levels are built on the template once, under the lock
+            if self.template is None:
+                self.template = Mesh(vtx, tet)
+            if r.level in self.built:
+                self.shared += 1
+            for lam in range(2, r.level + 1):
+                if lam not in self.built:
+                    self.template.layout(lam)
+                    self.built.add(lam)
+            r.mesh = Mesh(vtx, tet, like=self.template)
         r.op = Operator(r.mesh, r.level, method=TS_LSQP, q=self.q, sample_j=2,
                         fallback_tol=self.fallback_tol, stream=r.stream)
         r.sv = Solver(r.op, r.level, precision=self.precision, rtol=self.rtol,
@@ -134,6 +171,7 @@ class Server:
         reqs = [Request(rec, self.n_macros, self.precision) for rec in trace]
         pending = collections.deque(sorted(reqs, key=lambda r: r.t))
         waiting = collections.deque()
+        to_setup = []  # admitted, set-up not started: smallest level first
         setting_up = {}
         active = collections.defaultdict(list)
         grave = []
@@ -144,14 +182,14 @@ class Server:
         n_active = 0
         t0 = time.perf_counter()
         t_last = 0.0
-        while pending or waiting or setting_up or any(active.values()):
+        while pending or waiting or to_setup or setting_up or any(active.values()):
             now = time.perf_counter() - t0
             occ_area += n_active * (now - t_last)
             t_last = now
             while pending and pending[0].t <= now:
                 waiting.append(pending.popleft())
             # admission in arrival order, by slot and memory
-            while waiting and n_active + len(setting_up) < self.max_active:
+            while waiting and n_active + len(setting_up) + len(to_setup) < self.max_active:
                 r = waiting[0]
                 if used + r.bytes > self.hbm_budget:
                     if grave:
@@ -159,7 +197,7 @@ class Server:
                         self._destroy(grave)
                         grave = []
                         continue
-                    if n_active + len(setting_up) == 0:
+                    if n_active + len(setting_up) + len(to_setup) == 0:
                         raise RuntimeError("request %d needs %d bytes, over the HBM budget"
                                            % (r.id, r.bytes))
                     break
@@ -167,6 +205,11 @@ class Server:
                 used += r.bytes
                 peak_used = max(peak_used, used)
                 r.t_admit = now
+                to_setup.append(r)
+            # set-ups run on the worker threads, smallest level first
+            while to_setup and len(setting_up) < self.setup_workers:
+                r = min(to_setup, key=lambda q: (q.level, q.t))
+                to_setup.remove(r)
                 setting_up[self.pool.submit(self._setup, r)] = r
             # requests whose set-up finished join the active set
             for fut in [f for f in setting_up if f.done()]:
@@ -176,23 +219,34 @@ class Server:
                 active[r.level].append(r)
                 n_active += 1
             progressed = False
-            # one refinement iteration for every ready request, level by level
+            # retire finished requests; the others, smallest level first and
+            # in arrival order, get their next iteration while the work in
+            # flight stays within the budget
+            inflight = 0.0
+            ready = []
             for lvl in sorted(active):
                 still = []
                 for r in active[lvl]:
                     st = r.sv.query(r.info)
-                    if st == TS_SOLVE_READY:
-                        r.sv.step()
-                        progressed = True
-                        still.append(r)
-                    elif st == TS_SOLVE_DONE:
+                    if st == TS_SOLVE_DONE:
                         self._retire(r, time.perf_counter() - t0)
                         grave.append(r)
                         n_active -= 1
                         progressed = True
+                        continue
+                    still.append(r)
+                    if st == TS_SOLVE_READY:
+                        ready.append(r)
                     else:
-                        still.append(r)
+                        inflight += 8.0 ** (r.level - 7)
                 active[lvl] = still
+            for r in ready:  # already in priority order
+                w = 8.0 ** (r.level - 7)
+                if inflight > 0.0 and inflight + w > self.inflight_work:
+                    break
+                r.sv.step()
+                inflight += w
+                progressed = True
             if len(grave) >= self.gc_batch:
                 peak_dev = max(peak_dev, ts_device_bytes())
                 used -= sum(g.bytes for g in grave)
@@ -204,10 +258,14 @@ class Server:
         self._destroy(grave)
         torch.cuda.synchronize()
         t_end = time.perf_counter() - t0
-        return reqs, summarize(reqs, t_end, occ_area, peak_used, peak_dev)
+        summ = summarize(reqs, t_end, occ_area, peak_used, peak_dev)
+        summ["levels_shared"] = self.shared
+        return reqs, summ
 
     def close(self):
         self.pool.shutdown(wait=True)
+        self.template = None
+        self.built = set()
 
 
 def summarize(reqs, t_end, occ_area, peak_used, peak_dev):

@@ -54,6 +54,45 @@ def test_async_steps_match_blocking_solve(ts, prec):
     assert torch.equal(u1, u2)
 
 
+def test_mesh_with_new_vertices_matches_a_fresh_mesh(ts):
+    # the levels built on a mesh are kept when its vertices change, or shared
+    # by a mesh created like it; stored interface stencils, coordinates, fits
+    # and the coarse inverse follow each mesh's geometry: every result equals
+    # the one on a freshly built mesh
+    lam = 5
+    va, t = inputs.shell288(0.5, 1.0)
+    vb, _ = inputs.shell288(0.62, 1.0)
+    A = ts.Mesh(va, t)
+    op = ts.Operator(A, lam, method=ts.TS_LSQP, q=2, face_surrogate=True)
+    xa = A.to_block(lam, inputs.uniform(A.layout(lam).n_unique, 2))
+    op.apply(lam, xa)
+    ts.Operator(A, lam, method=ts.TS_IFEM).apply(lam, xa)  # stored coordinates, old geometry
+    with pytest.raises(ts.TSError) as e:  # an operator is still alive
+        A.set_vertices(vb)
+    assert e.value.code == ts.TS_EINVAL
+    del op
+    A.set_vertices(vb)
+    B = ts.Mesh(vb, t)
+    # a third mesh sharing B's built levels, with its own vertices
+    C = ts.Mesh(vb, None, like=B)
+    x = inputs.uniform(B.layout(lam).n_unique, 2)
+    f = B.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(3, 0.62))
+    assert torch.equal(A.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(3, 0.62)), f)
+    for kw in ({"method": ts.TS_LSQP}, {"method": ts.TS_LSQP, "face_surrogate": True},
+               {"method": ts.TS_IFEM}):
+        ob = ts.Operator(B, lam, q=2, **kw)
+        yb = ob.apply(lam, B.to_block(lam, x))
+        ub, rcb, ib = ts.Solver(ob, lam, rtol=1e-9, precision=ts.TS_F32).solve(f)
+        assert rcb == ts.TS_OK
+        for M in (A, C):
+            om = ts.Operator(M, lam, q=2, **kw)
+            assert torch.equal(om.apply(lam, M.to_block(lam, x)), yb)
+            um, rcm, im = ts.Solver(om, lam, rtol=1e-9, precision=ts.TS_F32).solve(f)
+            assert rcm == ts.TS_OK and im.cycles == ib.cycles and torch.equal(um, ub)
+            del om
+        del ob
+
+
 def _trace(n, rate, levels, seed=3):
     return inputs.serving_trace(n, rate=rate, seed=seed, levels=levels)
 
@@ -66,6 +105,7 @@ def test_served_alone_and_in_mix_are_bitwise_equal(ts):
     alone = Server(max_active=1, keep=keep)
     ra, sa = alone.run([rec for rec in trace if rec["id"] in keep])
     alone.close()
+    assert sa["levels_shared"] > 0  # later requests shared the built levels
     # mix: every request of the trace, many in flight
     mix = Server(max_active=24, keep=keep)
     rm, sm = mix.run(trace)

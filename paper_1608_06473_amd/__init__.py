@@ -108,6 +108,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libtwoscale.so is not built: run __graft_entry__.build() or "
                               "python paper_1608_06473_amd/build.py")
+        # PyTorch supplies the device memory and streams; its HIP runtime must
+        # be initialised before the library makes the first HIP call
+        import torch
+        torch.cuda.is_available()
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

@@ -155,6 +155,12 @@ def shell288(r_in=0.55, r_out=1.0):
     return cubed_shell(2, (r_in, 0.5 * (r_in + r_out), r_out))
 
 
+def shell2304(r_in=0.55, r_out=1.0):
+    """The 288-macro shell refined once in every direction: each cube face
+    split 4 x 4 and four radial layers at equal spacing (2,304 macros)."""
+    return cubed_shell(4, tuple(r_in + (r_out - r_in) * q / 4.0 for q in range(5)))
+
+
 def uniform(n, seed, lo=-1.0, hi=1.0):
     """n values ~ U[lo, hi) from NumPy's PCG64 generator with the given seed."""
     return np.random.default_rng(seed).uniform(lo, hi, size=int(n))

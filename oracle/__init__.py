@@ -28,7 +28,13 @@ DIRS = np.array(
 NAMES = ["mc", "mw", "me", "ms", "mn", "mse", "mnw", "bc", "be", "bn", "bnw", "tc", "tw",
          "ts", "tse"]
 
-IFEM, LSQP, IPOLY = 0, 1, 2
+IFEM, LSQP, IPOLY, SYM = 0, 1, 2, 3
+
+
+def _opkind(kind):
+    """operator kind of the C oracle: 0 element-wise, 1 surrogate (15
+    polynomials per macro), 2 symmetric surrogate (7 edge polynomials)"""
+    return 0 if kind == IFEM else 2 if kind == SYM else 1
 
 
 def build(force=False):
@@ -106,6 +112,9 @@ def lib():
             "or_face_row_exact": (I, [P, I, I64, P, P]),
             "or_face_fit_values": (I, [I, I, I, P, P]),
             "or_face_poly_eval": (D, [I, I, P, I, I]),
+            "or_fit_sym": (I, [P, I, I, I, P]),
+            "or_fit_sym_values": (I, [I, I, I, P, P]),
+            "or_poly_eval_mid": (D, [I, I, P, I, I, I, I]),
             "or_solve_dd": (I, [P, P, P, D, I, P]),
         }
         for name, (res, args) in sig.items():
@@ -198,6 +207,13 @@ class Mesh:
             raise ValueError("oracle fit failed (method %d, q %d)" % (method, q))
         return c
 
+    def fit_sym(self, N, q=2, jsamp=2):
+        """Pair polynomials of the symmetric surrogate: nt x 7 x m_q."""
+        c = np.zeros((self.nt, 7, num_coeffs(q)))
+        if lib().or_fit_sym(self.h, N, q, jsamp, _p(c)):
+            raise ValueError("oracle symmetric fit failed (q %d)" % q)
+        return c
+
     def face_fit(self, N, q=2, jsamp=2):
         """Per-face fits of the rows of interior-face nodes: nf x 15 x m2 in
         the face frame (zero for faces that are not fitted)."""
@@ -220,7 +236,7 @@ class Mesh:
         x = _f64(x)
         y = np.zeros_like(x)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
-        lib().or_apply(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(x), _p(y))
+        lib().or_apply(self.h, N, _opkind(kind), q, center, _p(cf), _p(x), _p(y))
         return y
 
     def apply_rows(self, N, x, rows, kind=IFEM, q=2, center=0, coeffs=None, flags=None,
@@ -230,7 +246,7 @@ class Mesh:
         rows = np.ascontiguousarray(rows, dtype=np.int64)
         y = np.zeros(rows.shape[0])
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
-        lib().or_apply_rows(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(x), _p(rows),
+        lib().or_apply_rows(self.h, N, _opkind(kind), q, center, _p(cf), _p(x), _p(rows),
                             rows.shape[0], _p(y))
         return y
 
@@ -240,7 +256,7 @@ class Mesh:
         f, u = _f64(f), _f64(u)
         r = np.zeros_like(u)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
-        lib().or_residual(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(f), _p(u), _p(r))
+        lib().or_residual(self.h, N, _opkind(kind), q, center, _p(cf), _p(f), _p(u), _p(r))
         return r
 
     def gs_sweep(self, N, f, u, kind=IFEM, q=2, center=0, coeffs=None, flags=None,
@@ -249,7 +265,7 @@ class Mesh:
         f = _f64(f)
         u = np.array(u, dtype=np.float64, copy=True)
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
-        lib().or_gs_sweep(self.h, N, 1 if kind else 0, q, center, _p(cf), _p(f), _p(u))
+        lib().or_gs_sweep(self.h, N, _opkind(kind), q, center, _p(cf), _p(f), _p(u))
         return u
 
     def prolongate(self, N, uc):
@@ -315,7 +331,7 @@ class Multigrid:
             else:
                 arr[l] = None
         self._arr = arr
-        self.h = lib().or_mg_new(mesh.h, lam0, lamL, 1 if kind else 0, q, center, nu1, nu2,
+        self.h = lib().or_mg_new(mesh.h, lam0, lamL, _opkind(kind), q, center, nu1, nu2,
                                  C.cast(arr, C.c_void_p))
         if flags is not None:
             for l in range(nl):
@@ -393,6 +409,19 @@ def face_sample_points(N, jsamp=2):
     p = np.zeros((n, 2), dtype=np.int32)
     lib().or_face_sample_points(N, jsamp, _p(p))
     return p
+
+
+def fit_sym_values(N, vals, q=2, jsamp=2):
+    """Pair polynomials (7 x m_q) fitted to values (ns x 15) at the LSQP
+    sampling points."""
+    c = np.zeros((7, num_coeffs(q)))
+    if lib().or_fit_sym_values(N, q, jsamp, _p(_f64(vals)), _p(c)):
+        raise ValueError("symmetric fit failed")
+    return c
+
+
+def poly_eval_mid(q, N, c, i, j, k, w):
+    return float(lib().or_poly_eval_mid(q, N, _p(_f64(c)), int(i), int(j), int(k), int(w)))
 
 
 def face_poly_eval(q, N, c, a, b):

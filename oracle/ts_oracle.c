@@ -730,6 +730,114 @@ int or_fit(const or_mesh *M, int N, int method, int q, int jsamp, double *coeffs
 }
 
 /* ------------------------------------------------------------------------ */
+/* symmetric surrogate (remark at the end of Sec. 3.3): one polynomial per   */
+/* edge direction, evaluated at the midpoint of the edge                     */
+/* ------------------------------------------------------------------------ */
+
+/* the direction opposite to w */
+static int dir_opposite(int w) {
+    for (int v = 0; v < NW; v++)
+        if (DIR[v][0] == -DIR[w][0] && DIR[v][1] == -DIR[w][1] && DIR[v][2] == -DIR[w][2])
+            return v;
+    return -1;
+}
+
+/* the seven edge directions: pair p joins directions w < w' = opposite(w) */
+static int sym_pairs(int pw[7][2]) {
+    int n = 0;
+    for (int w = 1; w < NW; w++) {
+        int o = dir_opposite(w);
+        if (o > w) { pw[n][0] = w; pw[n][1] = o; n++; }
+    }
+    return n;
+}
+
+/* pair index of direction w (1..14) */
+static int sym_pair_of(int w) {
+    int pw[7][2];
+    sym_pairs(pw);
+    for (int p = 0; p < 7; p++)
+        if (pw[p][0] == w || pw[p][1] == w) return p;
+    return -1;
+}
+
+/* The basis at the midpoint of the edge from (i, j, k) in direction w: the
+   point (i + w/2, ...) has index coordinates that are integers on the level
+   with 2N intervals, so the monomials are those of that level at
+   (2i + w_i, 2j + w_j, 2k + w_k). */
+static void basis_row_mid(int q, int N, int i, int j, int k, int w, double *row) {
+    basis_row(q, 2 * N, 2 * i + DIR[w][0], 2 * j + DIR[w][1], 2 * k + DIR[w][2], row);
+}
+
+/* Least-squares fit of the pair polynomials from values at the sampling
+   points: vals[s][w] is the exact weight of direction w at sample s, i.e. the
+   weight of the edge whose midpoint is sample + w/2; pair p is fitted to the
+   weights of its two directions at all samples (2 x ns points).  out:
+   7 x mq.  Returns 0 on success. */
+static int fit_sym_from(int N, int q, int64_t ns, const int *pts, const double *vals,
+                        double *out) {
+    int mq = or_num_coeffs(q);
+    int pw[7][2];
+    sym_pairs(pw);
+    double *A = malloc(sizeof(double) * 2 * ns * mq);
+    double *B = malloc(sizeof(double) * 2 * ns);
+    double X[64];
+    int err = 0;
+    for (int p = 0; p < 7 && !err; p++) {
+        for (int h = 0; h < 2; h++) {
+            int w = pw[p][h];
+            for (int64_t t = 0; t < ns; t++) {
+                basis_row_mid(q, N, pts[3 * t], pts[3 * t + 1], pts[3 * t + 2], w,
+                              A + (h * ns + t) * mq);
+                B[h * ns + t] = vals[t * NW + w];
+            }
+        }
+        err = householder_lsq((int)(2 * ns), mq, A, B, 1, X);
+        for (int c = 0; c < mq; c++) out[p * mq + c] = X[c];
+    }
+    free(A); free(B);
+    return err;
+}
+
+/* Fit the pair polynomials of every macro at N intervals (LSQP sampling with
+   jsamp); coeffs: nt x 7 x m_q.  Returns 0 on success. */
+int or_fit_sym(const or_mesh *M, int N, int q, int jsamp, double *coeffs) {
+    int mq = or_num_coeffs(q);
+    int64_t ns = or_sample_points(N, 1, jsamp, NULL);
+    int *pts = malloc(sizeof(int) * 3 * ns);
+    or_sample_points(N, 1, jsamp, pts);
+    double *V = malloc(sizeof(double) * ns * NW);
+    int err = 0;
+    for (int64_t t = 0; t < M->nt && !err; t++) {
+        for (int64_t s2 = 0; s2 < ns; s2++)
+            or_ifem_stencil(M, N, t, pts[3 * s2], pts[3 * s2 + 1], pts[3 * s2 + 2], V + s2 * NW);
+        err = fit_sym_from(N, q, ns, pts, V, coeffs + t * 7 * mq);
+    }
+    free(pts); free(V);
+    return err;
+}
+
+/* the same fit for given values (ns x 15) at the LSQP sampling points */
+int or_fit_sym_values(int N, int q, int jsamp, const double *vals, double *out) {
+    int64_t ns = or_sample_points(N, 1, jsamp, NULL);
+    int *pts = malloc(sizeof(int) * 3 * ns);
+    or_sample_points(N, 1, jsamp, pts);
+    int err = fit_sym_from(N, q, ns, pts, vals, out);
+    free(pts);
+    return err;
+}
+
+/* value of a polynomial (m_q coefficients) at the midpoint of the edge from
+   (i, j, k) in direction w */
+double or_poly_eval_mid(int q, int N, const double *a, int i, int j, int k, int w) {
+    double row[64];
+    basis_row_mid(q, N, i, j, k, w, row);
+    double s = 0;
+    for (int c = 0; c < or_num_coeffs(q); c++) s += a[c] * row[c];
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
 /* surrogate rows on interior faces (the remark after eq.                    */
 /* numInteriorPoints: the same fitting applies to face nodes)                */
 /* ------------------------------------------------------------------------ */
@@ -946,8 +1054,9 @@ int or_face_row_exact(const or_mesh *M, int N, int64_t u, double *s, int64_t *nb
 
 /* Operator on one level: kind 0 = IFEM everywhere; kind 1 = surrogate rows on
    the volume primitives (coefficients nt x 15 x m_q) with IFEM rows on the
-   lower primitives (Sec. 3.4).  center 0: own polynomial for mc; 1: mc from
-   the row sum (Alg. 1). */
+   lower primitives (Sec. 3.4); kind 2 = the symmetric surrogate (coefficients
+   nt x 7 x m_q, one per edge direction, centre from the row sum).  center 0:
+   own polynomial for mc; 1: mc from the row sum (Alg. 1). */
 typedef struct {
     int kind, q, center;
     const double *coeffs;
@@ -1042,10 +1151,31 @@ static void row_face_surrogate(const or_mesh *M, int N, const or_op *op, int64_t
     *off = of;
 }
 
+/* Symmetric surrogate row of the interior node (i, j, k) of macro t: the
+   weight of direction w is its pair polynomial at the midpoint of the edge,
+   the centre weight minus the sum of the others (coefficients nt x 7 x m_q). */
+static void row_surrogate_sym(const or_mesh *M, int N, const or_op *op, int64_t t, int i,
+                              int j, int k, const double *x, double *diag, double *off) {
+    int mq = or_num_coeffs(op->q);
+    const double *a = op->coeffs + t * 7 * mq;
+    double of = 0, sum = 0;
+    for (int w = 1; w < NW; w++) {
+        double sw = or_poly_eval_mid(op->q, N, a + sym_pair_of(w) * mq, i, j, k, w);
+        sum += sw;
+        int dir;
+        int64_t v = canon_d(M, N, t, i + DIR[w][0], j + DIR[w][1], k + DIR[w][2], &dir);
+        of += sw * (dir ? 0.0 : x[v]);
+    }
+    *diag = -sum;
+    *off = of;
+}
+
 /* row of the interior node (i, j, k) of macro t under op */
 static void row_volume(const or_mesh *M, int N, const or_op *op, int64_t t, int i, int j,
                        int k, const double *x, double *diag, double *off) {
-    if (op->kind == 1 && !(op->ifem && op->ifem[t])) {
+    if (op->kind == 2 && !(op->ifem && op->ifem[t])) {
+        row_surrogate_sym(M, N, op, t, i, j, k, x, diag, off);
+    } else if (op->kind == 1 && !(op->ifem && op->ifem[t])) {
         row_surrogate(M, N, op, t, i, j, k, x, diag, off);
     } else {
         int64_t ct[1] = {t};

@@ -657,3 +657,100 @@ def test_face_surrogate_row_sums_and_degree(orc):
         errs.append(np.abs(ys - yi)[lo:hi].max() / np.abs(yi[lo:hi]).max())
     assert errs[0] > 2 * errs[1] > 4 * errs[2] > 8 * errs[3] > 0
     assert errs[1] < 0.1
+
+
+# ---------------------------------------------------------------------------
+# symmetric surrogate (remark at the end of Sec. 3.3): one polynomial per
+# edge direction, evaluated at the edge midpoint; centre from the row sum
+
+# the 15 stencil directions (i, j, k) in the library's order
+_DIRS = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (1, -1, 0), (-1, 1, 0),
+         (0, 0, -1), (1, 0, -1), (0, 1, -1), (-1, 1, -1), (0, 0, 1), (-1, 0, 1), (0, -1, 1),
+         (1, -1, 1)]
+
+
+def _volume_block(orc, M, N, t, kind, cf):
+    """The operator restricted to the interior nodes of macro t (the paper's
+    L|_T), assembled column by column from applies to unit vectors."""
+    nvb = M.nv + M.ne * (N - 1) + M.nf * (N - 1) * (N - 2) // 2
+    V = (N - 1) * (N - 2) * (N - 3) // 6
+    ids = np.arange(nvb + t * V, nvb + (t + 1) * V)
+    A = np.zeros((V, V))
+    for c, J in enumerate(ids):
+        e = np.zeros(M.num_unique(N))
+        e[J] = 1.0
+        A[:, c] = M.apply(N, e, kind=kind, q=2, coeffs=cf)[ids]
+    return A
+
+
+def test_sym_surrogate_is_symmetric(orc):
+    # both rows of an edge evaluate the same polynomial at the same midpoint:
+    # L~|_T is symmetric, where the node-evaluated LSQP surrogate is not
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t)
+    N = 8
+    cs = M.fit_sym(N, 2, 2)
+    cl = M.fit(N, orc.LSQP, 2, 2)
+    for tt in (0, 137):
+        A = _volume_block(orc, M, N, tt, orc.SYM, cs)
+        assert np.linalg.norm(A - A.T) <= 1e-15 * np.linalg.norm(A)
+        B = _volume_block(orc, M, N, tt, orc.LSQP, cl)
+        assert np.linalg.norm(B - B.T) > 1e-4 * np.linalg.norm(B)
+
+
+def test_sym_fit_recovers_polynomial_edge_fields(orc):
+    # edge weights that are a degree-q polynomial of the edge midpoint (built
+    # here in raw powers of the midpoint coordinates / N, one polynomial per
+    # edge direction) are recovered exactly, at any node and direction
+    rng = np.random.default_rng(11)
+    N = 32
+    pts = orc.sample_points(N, orc.LSQP, 2)
+    opp = [0, 2, 1, 4, 3, 6, 5, 11, 12, 13, 14, 7, 8, 9, 10]
+    pair = {}
+    for w in range(1, 15):
+        pair[w] = min(w, opp[w])
+    for q in (1, 2, 3):
+        exps = [(a, b, c) for d in range(q + 1) for a in range(d + 1) for b in range(d + 1 - a)
+                for c in [d - a - b]]
+        C = {p: rng.uniform(-1, 1, len(exps)) for p in set(pair.values())}
+
+        def edge(p, mi, mj, mk):
+            return sum(C[p][n] * (mi / N) ** a * (mj / N) ** b * (mk / N) ** c
+                       for n, (a, b, c) in enumerate(exps))
+        vals = np.zeros((len(pts), 15))
+        for s_, (i, j, k) in enumerate(pts):
+            for w in range(1, 15):
+                di, dj, dk = _DIRS[w]
+                vals[s_, w] = edge(pair[w], i + di / 2, j + dj / 2, k + dk / 2)
+        c = orc.fit_sym_values(N, vals, q=q)
+        order = sorted(set(pair.values()))
+        for (i, j, k) in [(1, 1, 1), (5, 9, 3), (20, 4, 2)]:
+            for w in range(1, 15):
+                di, dj, dk = _DIRS[w]
+                got = orc.poly_eval_mid(q, N, c[order.index(pair[w])], i, j, k, w)
+                assert abs(got - edge(pair[w], i + di / 2, j + dj / 2, k + dk / 2)) < 1e-11
+
+
+def test_sym_surrogate_on_affine_mesh_is_exact(orc):
+    # Phi = Id: the edge weights are constant, so the symmetric surrogate is
+    # the exact operator
+    v, t = inputs.shell36()
+    M = orc.Mesh(v, t, affine=True)
+    N = 16
+    cs = M.fit_sym(N, 2, 2)
+    x = inputs.uniform(M.num_unique(N), 8)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    ys = M.apply(N, x, kind=orc.SYM, q=2, coeffs=cs)
+    assert np.abs(ys - yi).max() < 1e-12 * np.abs(yi).max()
+
+
+def test_sym_surrogate_accuracy_matches_lsqp(orc):
+    # the symmetric variant fits as well as the node-evaluated LSQP surrogate
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t)
+    N = 16
+    x = inputs.uniform(M.num_unique(N), 3)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    es = np.abs(M.apply(N, x, kind=orc.SYM, q=2, coeffs=M.fit_sym(N, 2, 2)) - yi).max()
+    el = np.abs(M.apply(N, x, kind=orc.LSQP, q=2, coeffs=M.fit(N, orc.LSQP, 2, 2)) - yi).max()
+    assert 0 < es < 1.5 * el

@@ -265,6 +265,14 @@ def main():
                          "volume_gbs": round(alg_bytes / (q4_vol / 1e3) / 1e9, 1)}
     log("q=4 apply: %.3f ms (volume %.3f ms)" % (q4_ms, q4_vol))
     del op4
+    # the symmetric surrogate (edge polynomials at the midpoints, centre from
+    # the row sum): the same volume kernel in its row-sum mode
+    opS = ts.Operator(G, lam, method=ts.TS_LSQP_SYM, q=q, sample_j=2)
+    ts.ts_apply(opS.h, lam, ts.TS_F64, xb, yb, stream)
+    sym_ms = time_events(lambda: ts.ts_apply(opS.h, lam, ts.TS_F64, xb, yb, stream), reps, stream)
+    extra["sym_apply"] = {"ms": round(sym_ms, 4), "gdofs": round(info.n_free / sym_ms / 1e6, 3)}
+    log("symmetric surrogate apply: %.3f ms (%.2f GDoF/s)" % (sym_ms, info.n_free / sym_ms / 1e6))
+    del opS
     # q = 2 with surrogate rows on the interior faces as well (FP64 apply,
     # residual and Gauss-Seidel sweep); its largest relative deviation from
     # the operator with exact face rows on this x

@@ -61,7 +61,12 @@ enum {
 };
 
 enum { TS_GEOM_SHELL = 0, TS_GEOM_AFFINE = 1 };
-enum { TS_IFEM = 0, TS_LSQP = 1, TS_IPOLY = 2 };
+/* TS_LSQP_SYM: the symmetric surrogate of the remark at the end of Sec. 3.3,
+ * one polynomial per edge direction evaluated at the edge midpoint, fitted by
+ * least squares like LSQP to the exact weights of both directions; the centre
+ * weight is minus the sum of the others (the operator's centre mode is set to
+ * TS_CENTER_ROWSUM), so the volume rows of a macro form a symmetric matrix. */
+enum { TS_IFEM = 0, TS_LSQP = 1, TS_IPOLY = 2, TS_LSQP_SYM = 3 };
 enum { TS_CENTER_POLY = 0, TS_CENTER_ROWSUM = 1 };
 enum { TS_F64 = 0, TS_F32 = 1, TS_F16W = 2 };
 enum { TS_RHS_MANUFACTURED = 0, TS_RHS_BUMPS = 1, TS_RHS_ONE = 2 };
@@ -78,7 +83,8 @@ typedef struct {
 } ts_layout_info;
 
 typedef struct {
-    int method;   /* TS_LSQP, TS_IPOLY or TS_IFEM (exact on-the-fly assembly) */
+    int method;   /* TS_LSQP, TS_IPOLY, TS_LSQP_SYM or TS_IFEM (exact on-the-fly
+                     assembly) */
     int q;        /* surrogate degree 1..4 (IPOLY: 2) */
     int sample_j; /* LSQP sampling set M_{m(l,j)}, m = min(l, max(1, j)) */
     int center;   /* TS_CENTER_POLY or TS_CENTER_ROWSUM */

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libtwoscale.so")
 
 TS_OK, TS_EINVAL, TS_ENOMEM, TS_EHIP, TS_ENOCONV, TS_ENONFINITE = range(6)
 TS_GEOM_SHELL, TS_GEOM_AFFINE = 0, 1
-TS_IFEM, TS_LSQP, TS_IPOLY = 0, 1, 2
+TS_IFEM, TS_LSQP, TS_IPOLY, TS_LSQP_SYM = 0, 1, 2, 3
 TS_CENTER_POLY, TS_CENTER_ROWSUM = 0, 1
 TS_F64, TS_F32, TS_F16W = 0, 1, 2
 TS_RHS_MANUFACTURED, TS_RHS_BUMPS, TS_RHS_ONE = 0, 1, 2

@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "ts_internal.h"
+#include "ts_face.h"
 
 namespace ts {
 
@@ -714,6 +715,145 @@ void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt,
     k_fit_gram<<<1, 256, 0, s>>>(N, q, pts, npts, work);
     k_fit_solve<<<nt, 256, 0, s>>>(N, q, pts, npts, B, work, coef);
     TS_HIP(hipGetLastError());
+}
+
+// Symmetric surrogate (the remark at the end of Sec. 3.3): one polynomial
+// per edge direction pair (w, wo), fitted to the exact weights of both
+// directions at the edge midpoints.  A midpoint i + w/2 is an integer point
+// of the level with 2N intervals, so the pair's points are given in doubled
+// coordinates and the ordinary basis rows of that level apply.  Right-hand
+// side of pair p: the first np points carry the weight of w at the samples,
+// the next np that of wo; Lf is the Cholesky factor of the pair's Gram
+// matrix.  coef7[m][p][c].
+__global__ __launch_bounds__(64) void k_fit_solve_pair(int N2, int q, const int* __restrict__ pts2,
+                                                       int np, const double* __restrict__ Bv,
+                                                       const double* __restrict__ Lf, int w,
+                                                       int wo, int p,
+                                                       double* __restrict__ coef7) {
+    __shared__ double R[35];
+    const int m = blockIdx.x;
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    const double* Bm = Bv + (size_t)m * np * NW;
+    for (int c = threadIdx.x; c < mq; c += blockDim.x) {
+        double sum = 0.0;
+        double row[35];
+        for (int t = 0; t < 2 * np; t++) {
+            basis_row(q, N2, pts2[3 * t], pts2[3 * t + 1], pts2[3 * t + 2], row);
+            sum += row[c] * Bm[(size_t)(t < np ? t : t - np) * NW + (t < np ? w : wo)];
+        }
+        R[c] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double z[35];
+    for (int ii = 0; ii < mq; ii++) {
+        double t = R[ii];
+        for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
+        z[ii] = t / Lf[ii * mq + ii];
+    }
+    for (int ii = mq - 1; ii >= 0; ii--) {
+        double t = z[ii];
+        for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
+        z[ii] = t / Lf[ii * mq + ii];
+    }
+    for (int c = 0; c < mq; c++) coef7[((size_t)m * 7 + p) * mq + c] = z[c];
+}
+
+__device__ __forceinline__ double binom_small(int n, int k) {
+    double r = 1.0;
+    for (int a = 1; a <= k; a++) r = r * (n - k + a) / a;
+    return r;
+}
+__device__ __forceinline__ double pow_small(double x, int n) {
+    double r = 1.0;
+    for (int a = 0; a < n; a++) r *= x;
+    return r;
+}
+
+// Per macro and direction w = 1..14: the pair polynomial of w translated by
+// half an edge, Q_w(xi) = P_pair(w)(xi + w / (2N)), so that its value at a
+// node is the pair polynomial at the midpoint of the node's edge in direction
+// w; the monomials are expanded binomially (same basis order as basis_row).
+__global__ __launch_bounds__(64) void k_sym_shift(const double* __restrict__ coef7,
+                                                  const int* __restrict__ pair_of, int nt, int q,
+                                                  int N, double* __restrict__ coef15) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nt * 14) return;
+    const int m = idx / 14, w = 1 + idx % 14;
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    const double* P = coef7 + ((size_t)m * 7 + pair_of[w]) * mq;
+    const double dx = 0.5 * kDI[w] / N, dy = 0.5 * kDJ[w] / N, dz = 0.5 * kDK[w] / N;
+    double* out = coef15 + ((size_t)m * NW + w) * mq;
+    int b = 0;
+    for (int d = 0; d <= q; d++)
+        for (int l = d; l >= 0; l--)
+            for (int mm = d - l; mm >= 0; mm--) {
+                const int n = d - l - mm;  // output monomial xi^l eta^mm zeta^n
+                double v = 0.0;
+                int a = 0;
+                for (int d2 = 0; d2 <= q; d2++)
+                    for (int l2 = d2; l2 >= 0; l2--)
+                        for (int m2 = d2 - l2; m2 >= 0; m2--, a++) {
+                            const int n2 = d2 - l2 - m2;
+                            if (l2 < l || m2 < mm || n2 < n) continue;
+                            v += P[a] * binom_small(l2, l) * binom_small(m2, mm) *
+                                 binom_small(n2, n) * pow_small(dx, l2 - l) *
+                                 pow_small(dy, m2 - mm) * pow_small(dz, n2 - n);
+                        }
+                out[b++] = v;
+            }
+}
+// centre polynomial: minus the sum of the 14 translated ones (row sum zero)
+__global__ void k_sym_centre(double* __restrict__ coef15, int nt, int mq) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nt * mq) return;
+    const int m = idx / mq, c = idx % mq;
+    double s = 0.0;
+    for (int w = 1; w < NW; w++) s += coef15[((size_t)m * NW + w) * mq + c];
+    coef15[(size_t)m * NW * mq + c] = -s;
+}
+
+void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv, int nt,
+                    double* coef15, hipStream_t s) {
+    const int np = (int)pts.size() / 3;
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    // the seven pairs (w < opposite(w)) and the pair of every direction
+    int pw[7][2], pair_of[NW] = {0};
+    int np7 = 0;
+    for (int w = 1; w < NW; w++)
+        for (int o = w + 1; o < NW; o++)
+            if (kDI[o] == -kDI[w] && kDJ[o] == -kDJ[w] && kDK[o] == -kDK[w]) {
+                pair_of[w] = pair_of[o] = np7;
+                pw[np7][0] = w;
+                pw[np7][1] = o;
+                np7++;
+            }
+    TS_REQUIRE(np7 == 7, TS_EINVAL, "direction table without seven opposite pairs");
+    DBuf<double> c7, work;
+    c7.alloc((size_t)nt * 7 * mq);
+    work.alloc((size_t)mq * mq);
+    DBuf<int> d2, dpair;
+    dpair.upload(std::vector<int>(pair_of, pair_of + NW));
+    for (int p = 0; p < 7; p++) {
+        std::vector<int> p2((size_t)6 * np);
+        for (int h = 0; h < 2; h++) {
+            const int w = pw[p][h];
+            for (int t = 0; t < np; t++) {
+                p2[3 * ((size_t)h * np + t)] = 2 * pts[3 * t] + kDI[w];
+                p2[3 * ((size_t)h * np + t) + 1] = 2 * pts[3 * t + 1] + kDJ[w];
+                p2[3 * ((size_t)h * np + t) + 2] = 2 * pts[3 * t + 2] + kDK[w];
+            }
+        }
+        d2.upload(p2);
+        k_fit_gram<<<1, 256, 0, s>>>(2 * N, q, d2.p, 2 * np, work.p);
+        k_fit_solve_pair<<<nt, 64, 0, s>>>(2 * N, q, d2.p, np, Bv, work.p, pw[p][0], pw[p][1],
+                                          p, c7.p);
+        TS_HIP(hipStreamSynchronize(s));  // d2 and work are reused by the next pair
+    }
+    k_sym_shift<<<(nt * 14 + 63) / 64, 64, 0, s>>>(c7.p, dpair.p, nt, q, N, coef15);
+    k_sym_centre<<<(nt * mq + 255) / 256, 256, 0, s>>>(coef15, nt, mq);
+    TS_HIP(hipGetLastError());
+    TS_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------- coarse level

@@ -133,7 +133,10 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         work.alloc((size_t)mq * mq);
         lo->coef64.alloc((size_t)M.nt * NW * mq);
         launch_sample(M, lam, dp.p, np, Bv.p, s);
-        launch_fit(N, q, dp.p, np, Bv.p, (int)M.nt, lo->coef64.p, work.p, s);
+        if (op->p.method == TS_LSQP_SYM)
+            launch_fit_sym(N, q, pts, Bv.p, (int)M.nt, lo->coef64.p, s);
+        else
+            launch_fit(N, q, dp.p, np, Bv.p, (int)M.nt, lo->coef64.p, work.p, s);
         std::vector<double> h((size_t)M.nt * NW * mq);
         TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         TS_HIP(hipStreamSynchronize(s));
@@ -494,8 +497,9 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
     return guarded([&] {
         TS_REQUIRE(mesh && p && out, TS_EINVAL, "null argument");
         TS_REQUIRE(max_level >= 2 && max_level <= 9, TS_EINVAL, "max_level must be in 2..9");
-        TS_REQUIRE(p->method == TS_IFEM || p->method == TS_LSQP || p->method == TS_IPOLY, TS_EINVAL,
-                   "bad method");
+        TS_REQUIRE(p->method == TS_IFEM || p->method == TS_LSQP || p->method == TS_IPOLY ||
+                       p->method == TS_LSQP_SYM,
+                   TS_EINVAL, "bad method");
         if (p->method != TS_IFEM) {
             TS_REQUIRE(p->q >= 1 && p->q <= 4, TS_EINVAL, "degree q must be in 1..4");
             TS_REQUIRE(p->method != TS_IPOLY || p->q == 2, TS_EINVAL, "IPOLY is defined for q = 2");
@@ -507,6 +511,8 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
         try {
             op->mesh = mesh;
             op->p = *p;
+            // the symmetric surrogate defines the centre weight by the row sum
+            if (p->method == TS_LSQP_SYM) op->p.center = TS_CENTER_ROWSUM;
             op->max_level = max_level;
             op->mq = p->method == TS_IFEM ? 0 : mq_of(p->q);
             for (int lam = 2; lam <= max_level; lam++) setup_level(op, lam, S(s));

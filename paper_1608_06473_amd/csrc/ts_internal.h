@@ -304,6 +304,10 @@ void launch_coords(const Mesh& M, int lam, double* xyz, hipStream_t s);
 void launch_rhs(const Mesh& M, int lam, int kind, const double* dpar, int npar, double* f,
                 hipStream_t s);
 void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s);
+// symmetric surrogate: pair fits at the edge midpoints, translated to the 15
+// per-direction polynomials [nt][15][mq] (centre: minus the sum)
+void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* B, int nt,
+                    double* coef15, hipStream_t s);
 void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt, double* coef,
                 double* work, hipStream_t s);
 void launch_dense_assemble_cp(const Mesh& M, int lam, const int* off, const int4* cp, int nfree,

@@ -1,0 +1,88 @@
+"""The symmetric surrogate (TS_LSQP_SYM, the remark at the end of Sec. 3.3)
+through the C ABI vs the oracle.
+
+Each side fits on its own (GPU: FP64 normal equations of the seven pair
+polynomials, translated on the device into the 15 per-direction polynomials
+of the volume kernel; oracle: Householder QR of the pair polynomials,
+evaluated at the edge midpoints).  As for the other own fits the weights
+agree to 1e-12 (q = 2) and 1e-10 (q = 4) relative to the largest weight:
+bounds 1.5e-11 and 1.5e-9 on the operator.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1608_06473_amd import inputs  # noqa: E402
+
+from test_gpu_parity import block_of, pair, rel  # noqa: E402
+
+OWN = {2: 1.5e-11, 4: 1.5e-9}
+
+
+@pytest.fixture(scope="module")
+def ts():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1608_06473_amd as m
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("name,lam,q", [("shell288", 4, 2), ("shell36", 4, 2), ("shell288", 5, 2),
+                                        ("shell288", 4, 4), ("single", 5, 2)])
+def test_apply_and_residual(ts, name, lam, q):
+    import oracle
+    G, O = pair(name)
+    N = 2 ** lam
+    op = ts.Operator(G, lam, method=ts.TS_LSQP_SYM, q=q)
+    c = O.fit_sym(N, q, 2)
+    nu = O.num_unique(N)
+    x, f = inputs.uniform(nu, 31), inputs.uniform(nu, 32)
+    yo = O.apply(N, x, kind=oracle.SYM, q=q, coeffs=c)
+    yb = op.apply(lam, G.to_block(lam, x)).cpu().numpy()
+    assert rel(yb, block_of(O, N, yo)) < OWN[q]
+    ro = O.residual(N, f, x, kind=oracle.SYM, q=q, coeffs=c)
+    rb = op.residual(lam, G.to_block(lam, f), G.to_block(lam, x)).cpu().numpy()
+    assert rel(rb, block_of(O, N, ro)) < OWN[q]
+
+
+def test_gauss_seidel_and_vcycle(ts):
+    import oracle
+    G, O = pair("shell288")
+    lam, N = 4, 16
+    op = ts.Operator(G, lam, method=ts.TS_LSQP_SYM, q=2)
+    cs = [None] + [O.fit_sym(2 ** l, 2, 2) for l in range(3, lam + 1)]
+    nu = O.num_unique(N)
+    u, f = inputs.uniform(nu, 4), inputs.uniform(nu, 5)
+    uo = O.gs_sweep(N, f, O.gs_sweep(N, f, u, kind=oracle.SYM, q=2, coeffs=cs[-1]),
+                    kind=oracle.SYM, q=2, coeffs=cs[-1])
+    ub = G.to_block(lam, u)
+    op.smooth(lam, G.to_block(lam, f), ub, sweeps=2)
+    assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < OWN[2]
+    fm = O.rhs(N, 0, [0.55, 1.0])
+    u0 = inputs.uniform(nu, 12) * 1e-3
+    mg = oracle.Multigrid(O, 2, lam, kind=oracle.SYM, q=2, coeffs=cs)
+    uo = mg.vcycle(fm, u0)
+    sv = ts.Solver(op, lam)
+    ub = G.to_block(lam, u0)
+    sv.vcycle(G.to_block(lam, fm), ub)
+    assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < 1e-10
+
+
+def test_level6_every_entry_and_solve(ts):
+    import oracle
+    G, O = pair("shell288")
+    lam, N = 6, 64
+    op = ts.Operator(G, lam, method=ts.TS_LSQP_SYM, q=2)
+    c = O.fit_sym(N, 2, 2)
+    x = inputs.uniform(O.num_unique(N), 0)
+    yo = O.apply(N, x, kind=oracle.SYM, q=2, coeffs=c)
+    yb = G.to_canon(lam, op.apply(lam, G.to_block(lam, x))).cpu().numpy()
+    assert rel(yb, yo) < OWN[2]
+    # the symmetric operator solves to the tolerance like the others
+    u, rc, info = ts.Solver(op, lam, rtol=1e-10).solve(G.rhs(lam, ts.TS_RHS_MANUFACTURED,
+                                                              [0.55, 1.0]))
+    assert rc == ts.TS_OK and info.cycles < 40

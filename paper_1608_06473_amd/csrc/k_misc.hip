@@ -928,6 +928,9 @@ __global__ __launch_bounds__(64) void k_bgj_diag(const double* __restrict__ A, i
         if (j < b) {
             const double nk = (j == k) ? 1.0 / piv : M[k][j] / piv;
             M[k][j] = nk;
+            // rows are independent: unrolled so that their LDS round trips
+            // overlap
+#pragma unroll 16
             for (int i = 0; i < b; i++)
                 if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - col[i] * nk;
         }

@@ -882,30 +882,6 @@ __global__ __launch_bounds__(64) void k_dense_assemble(const MacroGeom* __restri
     }
 }
 
-// Gauss-Jordan step k (no pivoting: the matrix is SPD): save column k,
-// scale row k by 1/A_kk (A_kk <- 1/A_kk) ...
-__global__ __launch_bounds__(256) void k_gj_pivot(double* A, double* col, int n, int k) {
-    const double piv = A[(size_t)k * n + k];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) col[i] = A[(size_t)i * n + k];
-    __syncthreads();
-    for (int jj = threadIdx.x; jj < n; jj += blockDim.x)
-        A[(size_t)k * n + jj] = (jj == k) ? 1.0 / piv : A[(size_t)k * n + jj] / piv;
-}
-// ... then eliminate column k from every other row
-__global__ __launch_bounds__(256) void k_gj_update(double* A, const double* __restrict__ col, int n, int k) {
-    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (jj >= n || i == k) return;
-    const double f = col[i];
-    const double a = (jj == k) ? 0.0 : A[(size_t)i * n + jj];
-    A[(size_t)i * n + jj] = a - f * A[(size_t)k * n + jj];
-}
-
-void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s) {
-    k_gj_pivot<<<1, 256, 0, s>>>(A, col, n, k);
-    k_gj_update<<<dim3((n + 255) / 256, n), 256, 0, s>>>(A, col, n, k);
-}
-
 // Blocked in-place Gauss-Jordan inversion of the SPD coarse matrix (row-major
 // n x n), pivot blocks K = k0 .. k0+b-1 of at most GJB rows in order:
 //   D = A[K,K]^-1;  P = D A[K,:];  A[i,j] -= A[i,K] P[:,j] (i, j outside K);

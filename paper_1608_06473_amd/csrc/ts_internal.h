@@ -313,7 +313,6 @@ void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt,
 void launch_dense_assemble_cp(const Mesh& M, int lam, const int* off, const int4* cp, int nfree,
                               const int* slot_free, double* A, hipStream_t s);
 void launch_transpose(const double* a, double* b, int n, hipStream_t s);
-void launch_gj_step(double* A, double* col, int n, int k, hipStream_t s);
 void launch_gj_blocked(double* A, int n, double* work, hipStream_t s);
 void launch_coarse_solve(const double* Ainv, int n, const int* free_first, const int* cp_off,
                          const int64_t* cp_slot, int dtype, const void* f, void* u,

@@ -829,11 +829,9 @@ void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv,
                 np7++;
             }
     TS_REQUIRE(np7 == 7, TS_EINVAL, "direction table without seven opposite pairs");
-    DBuf<double> c7, work;
-    c7.alloc((size_t)nt * 7 * mq);
-    work.alloc((size_t)mq * mq);
-    DBuf<int> d2, dpair;
-    dpair.upload(std::vector<int>(pair_of, pair_of + NW));
+    SBuf<double> c7((size_t)nt * 7 * mq, s), work((size_t)mq * mq, s);
+    const std::vector<int> hpair(pair_of, pair_of + NW);
+    SBuf<int> dpair(hpair, s), d2((size_t)6 * np, s);
     for (int p = 0; p < 7; p++) {
         std::vector<int> p2((size_t)6 * np);
         for (int h = 0; h < 2; h++) {
@@ -844,11 +842,11 @@ void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv,
                 p2[3 * ((size_t)h * np + t) + 2] = 2 * pts[3 * t + 2] + kDK[w];
             }
         }
-        d2.upload(p2);
+        TS_HIP(hipMemcpyAsync(d2.p, p2.data(), p2.size() * sizeof(int), hipMemcpyHostToDevice, s));
         k_fit_gram<<<1, 256, 0, s>>>(2 * N, q, d2.p, 2 * np, work.p);
         k_fit_solve_pair<<<nt, 64, 0, s>>>(2 * N, q, d2.p, np, Bv, work.p, pw[p][0], pw[p][1],
                                           p, c7.p);
-        TS_HIP(hipStreamSynchronize(s));  // d2 and work are reused by the next pair
+        TS_HIP(hipStreamSynchronize(s));  // p2, d2 and work are reused by the next pair
     }
     k_sym_shift<<<(nt * 14 + 63) / 64, 64, 0, s>>>(c7.p, dpair.p, nt, q, N, coef15);
     k_sym_centre<<<(nt * mq + 255) / 256, 256, 0, s>>>(coef15, nt, mq);

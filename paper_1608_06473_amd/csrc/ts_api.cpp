@@ -76,8 +76,7 @@ static void split_macros(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
     const int nt = (int)M.nt;
     lo.flags.assign(nt, 0);
     if (op->p.fallback_tol > 0) {
-        DBuf<unsigned char> d;
-        d.alloc(nt);
+        SBuf<unsigned char> d(nt, s);
         launch_fallback_check(M, lam, op->p.q, lo.coef64.p, op->p.fallback_tol, d.p, s);
         TS_HIP(hipMemcpyAsync(lo.flags.data(), d.p, nt, hipMemcpyDeviceToHost, s));
         TS_HIP(hipStreamSynchronize(s));
@@ -126,11 +125,8 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
         const int np = (int)pts.size() / 3;
         TS_REQUIRE(np >= mq, TS_EINVAL, "sampling set smaller than the polynomial space");
-        DBuf<int> dp;
-        dp.upload(pts);
-        DBuf<double> Bv, work;
-        Bv.alloc((size_t)M.nt * np * NW);
-        work.alloc((size_t)mq * mq);
+        SBuf<int> dp(pts, s);
+        SBuf<double> Bv((size_t)M.nt * np * NW, s), work((size_t)mq * mq, s);
         lo->coef64.alloc((size_t)M.nt * NW * mq);
         launch_sample(M, lam, dp.p, np, Bv.p, s);
         if (op->p.method == TS_LSQP_SYM)
@@ -302,16 +298,11 @@ static void coarse_setup(ts_solver* sv, hipStream_t s) {
         off.push_back((int)cp.size());
     }
     sv->n0 = n;
-    DBuf<int> d_off, d_sf;
-    DBuf<int4> d_cp;
-    d_off.upload(off);
-    d_cp.upload(cp);
-    d_sf.upload(slot_free);
+    SBuf<int> d_off(off, s), d_sf(slot_free, s);
+    SBuf<int4> d_cp(cp, s);
     sv->c_off.upload(off);
     sv->c_slot.upload(slot);
-    DBuf<double> A, work;
-    A.alloc((size_t)n * n);
-    work.alloc((size_t)64 * (n + 64));
+    SBuf<double> A((size_t)n * n, s), work((size_t)64 * (n + 64), s);
     TS_HIP(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), s));
     launch_dense_assemble_cp(M, lam, d_off.p, d_cp.p, n, d_sf.p, A.p, s);
     launch_gj_blocked(A.p, n, work.p, s);
@@ -486,8 +477,7 @@ int ts_rhs(ts_mesh* mesh, int level, int kind, const double* params, int nparams
             TS_REQUIRE(std::isfinite(params[i]), TS_ENONFINITE, "non-finite rhs parameter");
         std::vector<double> h(params ? params : nullptr, params ? params + nparams : nullptr);
         if (h.empty()) h.push_back(0.0);
-        DBuf<double> d;
-        d.upload(h);
+        SBuf<double> d(h, S(s));
         launch_rhs(mesh->m, level, kind, d.p, nparams, f, S(s));
         TS_HIP(hipStreamSynchronize(S(s)));
     });
@@ -642,9 +632,7 @@ int ts_norm2(ts_mesh* mesh, int level, int dtype, const void* x, double* out, ts
     return guarded([&] {
         TS_REQUIRE(mesh && x && out, TS_EINVAL, "null argument");
         check_dtype(dtype);
-        DBuf<double> part, r;
-        part.alloc(norm_partial_count(mesh->m, level));
-        r.alloc(1);
+        SBuf<double> part(norm_partial_count(mesh->m, level), S(s)), r(1, S(s));
         launch_norm2_free(mesh->m, level, dtype == TS_F64 ? TS_F64 : TS_F32, x, part.p, r.p, S(s));
         TS_HIP(hipMemcpyAsync(out, r.p, sizeof(double), hipMemcpyDeviceToHost, S(s)));
         TS_HIP(hipStreamSynchronize(S(s)));

@@ -71,6 +71,39 @@ struct DBuf {
     }
 };
 
+// Stream-ordered temporary device buffer: allocated and freed in the order of
+// stream s (hipMallocAsync / hipFreeAsync), so releasing it waits for nothing
+// but s, where a plain hipFree would wait for the whole device (set-up work of
+// one request then stalls behind every other request's queued kernels).
+// Every use must be ordered on s; upload() copies asynchronously on s, so the
+// host vector must outlive the next synchronisation of s.
+template <class X>
+struct SBuf {
+    X* p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+    SBuf(size_t count, hipStream_t st) : n(count), s(st) {
+        if (!count) return;
+        if (hipMallocAsync((void**)&p, count * sizeof(X), s) != hipSuccess) {
+            p = nullptr;
+            throw Error{TS_ENOMEM, "hipMallocAsync of " + std::to_string(count * sizeof(X)) +
+                                       " bytes failed"};
+        }
+        g_dev_bytes += (int64_t)(count * sizeof(X));
+    }
+    SBuf(const std::vector<X>& h, hipStream_t st) : SBuf(h.size(), st) {
+        if (n) TS_HIP(hipMemcpyAsync(p, h.data(), n * sizeof(X), hipMemcpyHostToDevice, s));
+    }
+    SBuf(const SBuf&) = delete;
+    SBuf& operator=(const SBuf&) = delete;
+    ~SBuf() {
+        if (p) {
+            (void)hipFreeAsync(p, s);
+            g_dev_bytes -= (int64_t)(n * sizeof(X));
+        }
+    }
+};
+
 // Per-macro topology record on the device: global vertex ids, edge and face
 // ids of the primitives (local edge order (0,1),(0,2),(0,3),(1,2),(1,3),(2,3);
 // face o is opposite local vertex o), which local vertex of each edge has the

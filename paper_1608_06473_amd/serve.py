@@ -121,6 +121,10 @@ class Server:
         self.shared = 0       # requests whose levels were all built already
         self.setup_workers = setup_workers
         self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
+        # retired requests are released on a thread of their own: freeing
+        # device memory waits for the device, and the scheduler must not
+        self.reaper = cf.ThreadPoolExecutor(max_workers=1)
+        self.reaping = []
 
     # -- per request ---------------------------------------------------------
     def _setup(self, r):
@@ -158,10 +162,14 @@ class Server:
                 r.u_host = r.u.cpu().numpy()
 
     @staticmethod
-    def _destroy(reqs):
+    def _destroy_now(reqs):
         for r in reqs:
             r.sv = r.op = r.mesh = r.f = r.u = None
             r.stream = None
+
+    def _destroy(self, reqs):
+        self.reaping = [f for f in self.reaping if not f.done()]
+        self.reaping.append(self.reaper.submit(self._destroy_now, list(reqs)))
 
     # -- loop ----------------------------------------------------------------
     def run(self, trace):
@@ -256,6 +264,9 @@ class Server:
                 time.sleep(50e-6)
         peak_dev = max(peak_dev, ts_device_bytes())
         self._destroy(grave)
+        for fut in self.reaping:
+            fut.result()
+        self.reaping = []
         torch.cuda.synchronize()
         t_end = time.perf_counter() - t0
         summ = summarize(reqs, t_end, occ_area, peak_used, peak_dev)
@@ -264,6 +275,7 @@ class Server:
 
     def close(self):
         self.pool.shutdown(wait=True)
+        self.reaper.shutdown(wait=True)
         self.template = None
         self.built = set()
 

@@ -272,6 +272,15 @@ enum { TS_SOLVE_RUNNING = 1, TS_SOLVE_READY = 2, TS_SOLVE_DONE = 3 };
 int ts_solve_begin(ts_solver *sv, const double *f, double *u, ts_stream s);
 int ts_solve_step(ts_solver *sv);
 int ts_solve_query(ts_solver *sv, int *state, ts_solve_info *info);
+/* The batched step of a request loop: one outer iteration on each of the n
+ * distinct solvers v[0..n-1], enqueued in the order given (the loop's
+ * priority order).  Every solver must be TS_SOLVE_READY; otherwise nothing
+ * is enqueued and TS_EINVAL is returned.  Each solver's launches go to its
+ * own stream: requests carry their own meshes and coefficients, so no
+ * launch spans two of them, and the hardware queues overlap the streams.
+ * A HIP error part-way returns TS_EHIP with the solvers before the failing
+ * one stepped (their state is then TS_SOLVE_RUNNING).  n = 0 is a no-op. */
+int ts_solve_batch_step(ts_solver *const *v, int n);
 
 /* device memory currently held by all meshes, operators and solvers of the
  * process (bytes; excludes the caller's vectors) */

@@ -94,6 +94,7 @@ _SIGS = {
     "ts_solve_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_solve_step": (C.c_int, [C.c_void_p]),
     "ts_solve_query": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ts_solve_batch_step": (C.c_int, [C.c_void_p, C.c_int]),
     "ts_device_bytes": (C.c_int, [C.c_void_p]),
 }
 
@@ -301,6 +302,14 @@ def ts_solve_query(sv, info=None):
     st = C.c_int(0)
     _check(lib().ts_solve_query(sv, C.byref(st), C.byref(info) if info is not None else None))
     return st.value
+
+
+def ts_solve_batch_step(solvers):
+    """One outer iteration on each solver (handles or Solver objects), in
+    the order given; all must be ready, else nothing is enqueued."""
+    hs = [getattr(v, "h", v) for v in solvers]
+    arr = (C.c_void_p * max(len(hs), 1))(*hs)
+    return _check(lib().ts_solve_batch_step(arr, len(hs)))
 
 
 def ts_device_bytes():

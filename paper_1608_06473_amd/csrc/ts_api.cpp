@@ -838,6 +838,22 @@ int ts_solve_step(ts_solver* sv) {
     });
 }
 
+int ts_solve_batch_step(ts_solver* const* v, int n) {
+    return guarded([&] {
+        TS_REQUIRE(n >= 0 && (n == 0 || v), TS_EINVAL, "bad arguments");
+        std::vector<const ts_solver*> seen(v, v + n);
+        std::sort(seen.begin(), seen.end());
+        TS_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), TS_EINVAL,
+                   "a solver appears twice in the batch");
+        for (int a = 0; a < n; a++) {
+            TS_REQUIRE(v[a], TS_EINVAL, "null solver in the batch");
+            TS_REQUIRE(v[a]->state == TS_SOLVE_READY, TS_EINVAL,
+                       "a solver in the batch is not ready for a step");
+        }
+        for (int a = 0; a < n; a++) solve_step(v[a]);
+    });
+}
+
 int ts_solve_query(ts_solver* sv, int* state, ts_solve_info* info) {
     return guarded([&] {
         TS_REQUIRE(sv && state, TS_EINVAL, "null argument");

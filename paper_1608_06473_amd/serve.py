@@ -6,7 +6,8 @@ HBM budget and a slot is free.  A worker thread then builds its mesh,
 surrogate operator and multigrid solver on the request's own stream, and
 enqueues the start of the solve (ts_solve_begin).  The scheduler thread polls
 every active solve without blocking (ts_solve_query) and enqueues the next
-refinement iteration (ts_solve_step) of requests whose last one has finished,
+refinement iteration of requests whose last one has finished, in one batched
+call (ts_solve_batch_step),
 smallest level first and, within a level, in arrival order, as long as the
 work in flight stays under a budget (an iteration at level l counts
 8^(l - 7), so about two level-7 iterations run at once while small requests
@@ -34,7 +35,8 @@ import time
 import numpy as np
 
 from . import (TS_F32, TS_F64, TS_LSQP, TS_OK, TS_RHS_BUMPS, TS_SOLVE_DONE, TS_SOLVE_READY,
-               Mesh, Operator, Solver, inputs, ts_device_bytes, ts_solve_info)
+               Mesh, Operator, Solver, inputs, ts_device_bytes, ts_solve_batch_step,
+               ts_solve_info)
 
 TOPOLOGIES = {
     # the 288-macro shell (faces split 2 x 2, two radial layers) scaled to the
@@ -248,12 +250,15 @@ class Server:
                     else:
                         inflight += 8.0 ** (r.level - 7)
                 active[lvl] = still
+            batch = []
             for r in ready:  # already in priority order
                 w = 8.0 ** (r.level - 7)
                 if inflight > 0.0 and inflight + w > self.inflight_work:
                     break
-                r.sv.step()
+                batch.append(r.sv)
                 inflight += w
+            if batch:
+                ts_solve_batch_step(batch)
                 progressed = True
             if len(grave) >= self.gc_batch:
                 peak_dev = max(peak_dev, ts_device_bytes())

@@ -1,7 +1,7 @@
 """Asynchronous solves and the continuous-batching request loop.
 
-- the non-blocking begin / step / query sequence reproduces the blocking
-  solve bitwise;
+- the non-blocking begin / step / query sequence, and the batched step over
+  several solvers, reproduce the blocking solves bitwise;
 - requests solved alone and inside a mix of concurrent requests give bitwise
   identical solutions (tolerance 0: no atomics, fixed reduction order);
 - the oracle's operator measures the residual of a served solution.
@@ -52,6 +52,57 @@ def test_async_steps_match_blocking_solve(ts, prec):
     assert info2.status == ts.TS_OK and steps == info1.cycles == info2.cycles
     assert info2.rel_residual == info1.rel_residual
     assert torch.equal(u1, u2)
+
+
+def test_batched_steps_match_blocking_solves(ts):
+    # three solves (two meshes, two levels, two precisions) on streams of
+    # their own, advanced only through the batched step: each ends bitwise
+    # where its blocking solve ends
+    cases = []
+    for r_in, lam, prec, seed in ((0.5, 5, 1, 3), (0.6, 4, 0, 4), (0.5, 4, 1, 5)):
+        v, t = inputs.shell288(r_in, 1.0)
+        G = ts.Mesh(v, t)
+        op = ts.Operator(G, lam, method=ts.TS_LSQP, q=2)
+        sv = ts.Solver(op, lam, precision=prec, rtol=1e-8)
+        f = G.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(seed, r_in))
+        u1, rc, info1 = sv.solve(f)
+        assert rc == ts.TS_OK
+        cases.append((G, op, sv, f, u1, info1))
+    ts.ts_solve_batch_step([])  # empty batch: nothing to do
+    run = []
+    for G, op, sv, f, u1, info1 in cases:
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            u2 = G.zeros(sv.level)
+        sv.begin(f, u2, s)
+        run.append((sv, u2, ts.ts_solve_info()))
+    # a batch holding a solver that is still running, or one solver twice,
+    # is refused whole
+    torch.cuda.synchronize()
+    assert all(sv.query() == ts.TS_SOLVE_READY for sv, _, _ in run)
+    ts.ts_solve_batch_step([run[0][0]])
+    for bad in ([run[1][0], run[0][0]], [run[1][0], run[1][0]]):
+        with pytest.raises(ts.TSError) as e:
+            ts.ts_solve_batch_step(bad)
+        assert e.value.code == ts.TS_EINVAL
+    torch.cuda.synchronize()
+    assert run[1][0].query() == ts.TS_SOLVE_READY  # not stepped by the refused calls
+    while True:
+        ready, live = [], 0
+        for sv, _, info in run:
+            st = sv.query(info)
+            if st != ts.TS_SOLVE_DONE:
+                live += 1
+            if st == ts.TS_SOLVE_READY:
+                ready.append(sv)
+        if not live:
+            break
+        ts.ts_solve_batch_step(ready)
+    torch.cuda.synchronize()
+    for (G, op, sv, f, u1, info1), (_, u2, info2) in zip(cases, run):
+        assert info2.status == ts.TS_OK and info2.cycles == info1.cycles
+        assert info2.rel_residual == info1.rel_residual
+        assert torch.equal(u1, u2)
 
 
 def test_mesh_with_new_vertices_matches_a_fresh_mesh(ts):

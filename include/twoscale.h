@@ -191,7 +191,10 @@ int ts_node_coords(ts_mesh *mesh, int level, double *xyz, ts_stream s);
  *       params = {r1, r2};
  *   TS_RHS_BUMPS: sum of Gaussians a exp(-|x - c|^2 / (2 s^2)), params =
  *       records (cx, cy, cz, s, a);
- *   TS_RHS_ONE: f = 1. */
+ *   TS_RHS_ONE: f = 1.
+ * f is evaluated once per block slot into a temporary of one block vector
+ * (allocated and freed in stream order on s, TS_ENOMEM if it does not fit);
+ * the call returns once f is written. */
 int ts_rhs(ts_mesh *mesh, int level, int kind, const double *params, int nparams, double *f,
            ts_stream s);
 

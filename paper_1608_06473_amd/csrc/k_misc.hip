@@ -504,21 +504,41 @@ __device__ __forceinline__ double rhs_point(int kind, const double* par, int np,
     return 1.0;
 }
 
+// f at every slot of every macro block, from that macro's blended
+// coordinates: each point is evaluated once, and the mass rows below read
+// these values instead of evaluating f at all 15 points of every row
+__global__ __launch_bounds__(256) void k_rhs_nodal(double* __restrict__ fv,
+                                                   const MacroGeom* __restrict__ geom,
+                                                   const int2* __restrict__ slot_tiles, int N,
+                                                   int64_t B, int kind,
+                                                   const double* __restrict__ par, int np) {
+    TS_SLOT_DECODE();
+    double x[3];
+    node_xyz(geom[macro], N, i, j, k, x);
+    fv[slot] = rhs_point(kind, par, np, x);
+}
+
 // partial consistent-mass row of local node (i,j,k) of one macro applied to
-// the nodal values of f: sum_T |T|/20 (2 f_I + sum_{J in T, J != I} f_J)
-__device__ double mass_partial(const MacroGeom& g, int N, int i, int j, int k,
-                               int kind, const double* par, int np) {
+// the nodal values of f (fvb: that macro's block of them):
+// sum_T |T|/20 (2 f_I + sum_{J in T, J != I} f_J).  Both loops are unrolled
+// so that the points stay in registers.
+__device__ __forceinline__ double mass_partial(const MacroGeom& g, int N, int i, int j, int k,
+                                               const double* __restrict__ fvb) {
     double xs[NW][3], fv[NW];
     unsigned valid = 0;
+#pragma unroll
     for (int w = 0; w < NW; w++) {
         const int a = i + dir_i(w), b = j + dir_j(w), c = k + dir_k(w);
+        xs[w][0] = xs[w][1] = xs[w][2] = 0.0;
+        fv[w] = 0.0;
         if (inside(N, a, b, c)) {
             valid |= 1u << w;
             node_xyz(g, N, a, b, c, xs[w]);
-            fv[w] = rhs_point(kind, par, np, xs[w]);
+            fv[w] = fvb[bidx(N, a, b, c)];
         }
     }
     double s = 0.0;
+#pragma unroll
     for (int t = 0; t < 24; t++) {
         const int w0 = kTets24.t[t][0], w1 = kTets24.t[t][1], w2 = kTets24.t[t][2],
                   w3 = kTets24.t[t][3];
@@ -533,26 +553,25 @@ __device__ double mass_partial(const MacroGeom& g, int N, int i, int j, int k,
 
 __global__ __launch_bounds__(256) void k_rhs_volume(double* __restrict__ f, const MacroGeom* __restrict__ geom,
                                                     const int2* __restrict__ slot_tiles,
-                                                    int N, int64_t B, int kind,
-                                                    const double* __restrict__ par, int np) {
+                                                    int N, int64_t B,
+                                                    const double* __restrict__ fv) {
     TS_SLOT_DECODE();
     if (i < 1 || j < 1 || k < 1 || i + j + k > N - 1) return;
-    f[slot] = mass_partial(geom[macro], N, i, j, k, kind, par, np);
+    f[slot] = mass_partial(geom[macro], N, i, j, k, fv + (size_t)macro * B);
 }
 
 __global__ __launch_bounds__(256) void k_rhs_iface(double* __restrict__ f, const MacroGeom* __restrict__ geom,
                                                    const int* __restrict__ off,
                                                    const int4* __restrict__ cp,
                                                    const unsigned char* __restrict__ flag, int n, int N,
-                                                   int64_t B, int kind, const double* __restrict__ par,
-                                                   int np) {
+                                                   int64_t B, const double* __restrict__ fv) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     double v = 0.0;
     if (!(flag[t] & 1))
         for (int c = off[t]; c < off[t + 1]; c++) {
             const int4 q = cp[c];
-            v += mass_partial(geom[q.x], N, q.y, q.z, q.w, kind, par, np);
+            v += mass_partial(geom[q.x], N, q.y, q.z, q.w, fv + (size_t)q.x * B);
         }
     for (int c = off[t]; c < off[t + 1]; c++) {
         const int4 q = cp[c];
@@ -564,9 +583,11 @@ void launch_rhs(const Mesh& M, int lam, int kind, const double* dpar, int npar, 
                 hipStream_t s) {
     const Level& L = const_cast<Mesh&>(M).level(lam);
     const dim3 g(L.n_slot_tiles, (unsigned)M.nt);
-    k_rhs_volume<<<g, 256, 0, s>>>(f, M.d_geom.p, L.slot_tiles.p, L.N, L.B, kind, dpar, npar);
+    SBuf<double> fv((size_t)L.len, s);
+    k_rhs_nodal<<<g, 256, 0, s>>>(fv.p, M.d_geom.p, L.slot_tiles.p, L.N, L.B, kind, dpar, npar);
+    k_rhs_volume<<<g, 256, 0, s>>>(f, M.d_geom.p, L.slot_tiles.p, L.N, L.B, fv.p);
     const int n = (int)L.n_if;
-    if (n) k_rhs_iface<<<(n + 255) / 256, 256, 0, s>>>(f, M.d_geom.p, L.if_off.p, L.if_copy.p, L.if_flag.p, n, L.N, L.B, kind, dpar, npar);
+    if (n) k_rhs_iface<<<(n + 255) / 256, 256, 0, s>>>(f, M.d_geom.p, L.if_off.p, L.if_copy.p, L.if_flag.p, n, L.N, L.B, fv.p);
     TS_HIP(hipGetLastError());
 }
 

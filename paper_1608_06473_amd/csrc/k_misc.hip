@@ -28,6 +28,18 @@ __device__ __forceinline__ void plane_pos_to_ij(int r, int A, int& i, int& j) {
     i = r - J * (2 * A - J + 1) / 2;
 }
 
+// 32-bit block indices for the slot and transfer kernels: levels go up to 9
+// (N <= 512), where every index of a block stays below 2^25 and
+// n (n + 1) (n + 2) below 2^28, so no 64-bit products or divisions are needed
+__device__ __forceinline__ unsigned tet32(unsigned n) { return n * (n + 1u) * (n + 2u) / 6u; }
+__device__ __forceinline__ int plane_off32(int N, int k) {
+    return (int)(tet32((unsigned)N + 1u) - tet32((unsigned)(N + 1 - k)));
+}
+__device__ __forceinline__ int bidx32(int N, int i, int j, int k) {
+    const unsigned a = (unsigned)(N + 1 - k), uj = (unsigned)j;
+    return plane_off32(N, k) + (int)(uj * a - (uj * (uj - 1u)) / 2u) + i;
+}
+
 // all-slot kernels: grid = n_macros x n_slot_tiles (tiles of plane k)
 #define TS_SLOT_DECODE(L_ARGS)                                                       \
     const int macro = blockIdx.y;                                                    \
@@ -38,7 +50,7 @@ __device__ __forceinline__ void plane_pos_to_ij(int r, int A, int& i, int& j) {
     if (r >= A * (A + 1) / 2) return;                                                \
     int i, j;                                                                        \
     plane_pos_to_ij(r, A, i, j);                                                     \
-    const size_t slot = (size_t)macro * B + plane_off(N, k) + r;
+    const size_t slot = (size_t)macro * B + (size_t)(plane_off32(N, k) + r);
 
 // ---------------------------------------------------------------- transfers
 
@@ -55,10 +67,11 @@ __global__ __launch_bounds__(256) void k_restrict_volume(
     if (i < 1 || j < 1 || k < 1 || i + j + k > Nc - 1) return;
     const int Nf = 2 * Nc;
     const T* fm = rf + (size_t)macro * Bf;
-    T s = fm[bidx(Nf, 2 * i, 2 * j, 2 * k)];
+    T s = fm[bidx32(Nf, 2 * i, 2 * j, 2 * k)];
     T h = (T)0;
 #pragma unroll
-    for (int w = 1; w < NW; w++) h += fm[bidx(Nf, 2 * i + dir_i(w), 2 * j + dir_j(w), 2 * k + dir_k(w))];
+    for (int w = 1; w < NW; w++)
+        h += fm[bidx32(Nf, 2 * i + dir_i(w), 2 * j + dir_j(w), 2 * k + dir_k(w))];
     rc[slot] = s + (T)0.5 * h;
 }
 
@@ -97,7 +110,7 @@ __device__ __forceinline__ double restrict_copy(const T* __restrict__ rf, int4 q
     for (int w = 1; w < NW; w++) {
         if (!inside(Nc, q.y + dir_i(w), q.z + dir_j(w), q.w + dir_k(w))) continue;
         const int a = 2 * q.y + dir_i(w), b = 2 * q.z + dir_j(w), cc = 2 * q.w + dir_k(w);
-        v += 0.5 * (double)fm[bidx(Nf, a, b, cc)] / (double)node_mult(TP, Nf, a, b, cc);
+        v += 0.5 * (double)fm[bidx32(Nf, a, b, cc)] / (double)node_mult(TP, Nf, a, b, cc);
     }
     return v;
 }
@@ -110,11 +123,11 @@ __global__ __launch_bounds__(256) void k_restrict_face2(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n2) return;
     const int4 qa = cp[t], qb = cp[(size_t)n2 + t];
-    double v = (double)rf[(size_t)qa.x * Bf + bidx(2 * Nc, 2 * qa.y, 2 * qa.z, 2 * qa.w)];
+    double v = (double)rf[(size_t)qa.x * Bf + bidx32(2 * Nc, 2 * qa.y, 2 * qa.z, 2 * qa.w)];
     v += restrict_copy(rf, qa, topo[qa.x], Nc, Bf);
     v += restrict_copy(rf, qb, topo[qb.x], Nc, Bf);
-    rc[(size_t)qa.x * Bc + bidx(Nc, qa.y, qa.z, qa.w)] = (T)v;
-    rc[(size_t)qb.x * Bc + bidx(Nc, qb.y, qb.z, qb.w)] = (T)v;
+    rc[(size_t)qa.x * Bc + bidx32(Nc, qa.y, qa.z, qa.w)] = (T)v;
+    rc[(size_t)qb.x * Bc + bidx32(Nc, qb.y, qb.z, qb.w)] = (T)v;
 }
 
 // other free coarse interface nodes (edges, vertices): one wavefront per
@@ -134,10 +147,10 @@ __global__ __launch_bounds__(256) void k_restrict_rest(
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
     const int4 q0 = cp[c0];
-    v += (double)rf[(size_t)q0.x * Bf + bidx(2 * Nc, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
+    v += (double)rf[(size_t)q0.x * Bf + bidx32(2 * Nc, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
     for (int c = c0 + lane; c < c1; c += 64) {
         const int4 q = cp[c];
-        rc[(size_t)q.x * Bc + bidx(Nc, q.y, q.z, q.w)] = (T)v;
+        rc[(size_t)q.x * Bc + bidx32(Nc, q.y, q.z, q.w)] = (T)v;
     }
 }
 
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(256) void k_prolongate_add(
     const int pi = i & 1, pj = j & 1, pk = k & 1;
     T v;
     if (!(pi | pj | pk)) {
-        v = cm[bidx(Nc, i / 2, j / 2, k / 2)];
+        v = cm[bidx32(Nc, i / 2, j / 2, k / 2)];
     } else {
         // the lattice edge direction with this parity pattern
         int di, dj, dk;
@@ -172,8 +185,8 @@ __global__ __launch_bounds__(256) void k_prolongate_add(
         else if (pi && !pj && pk) { di = -1; dj = 0; dk = 1; }
         else if (!pi && pj && pk) { di = 0; dj = -1; dk = 1; }
         else { di = 1; dj = -1; dk = 1; }
-        const T a = cm[bidx(Nc, (i - di) / 2, (j - dj) / 2, (k - dk) / 2)];
-        const T b = cm[bidx(Nc, (i + di) / 2, (j + dj) / 2, (k + dk) / 2)];
+        const T a = cm[bidx32(Nc, (i - di) / 2, (j - dj) / 2, (k - dk) / 2)];
+        const T b = cm[bidx32(Nc, (i + di) / 2, (j + dj) / 2, (k + dk) / 2)];
         v = (T)0.5 * (a + b);
     }
     uf[slot] += v;

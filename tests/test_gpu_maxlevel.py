@@ -1,6 +1,7 @@
 """The largest levels through the C ABI vs the oracle: the wider staging of
 the surrogate volume kernel (4 entries per lane from level 8 on, 8 at level
-9) and the largest blocks.
+9), the largest blocks, and the transfers and load vector (32-bit block
+indices) at those sizes.
 
 One macro at levels 8 and 9 (N = 512: 22.6 M nodes) and the 36-macro shell
 at level 8 (36 macros, not a multiple of the 8 XCDs: a ragged launch), with
@@ -24,7 +25,7 @@ torch = pytest.importorskip("torch")
 from paper_1608_06473_amd import inputs  # noqa: E402
 
 from test_gpu_fullsize import _sample_rows  # noqa: E402
-from test_gpu_parity import TOL, pair, rel  # noqa: E402
+from test_gpu_parity import TOL, block_of, pair, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -85,3 +86,38 @@ def test_largest_levels_sampled(ts, name, lam):
     diag = np.array([oracle.poly_eval(2, N, c[t][0], i, j, k) for t, i, j, k in nodes])
     expect = x[grow] + (f[grow] - lo) / diag
     assert rel(uc[grow], expect) < TOL
+
+
+@pytest.mark.parametrize("name,lam", [("single", 8), ("single", 9), ("shell36", 7)])
+def test_transfers_largest_levels(ts, name, lam):
+    """R = P^T and u_f += P u_c against the oracle on every entry (FP64);
+    the 36-macro shell adds the face and edge rows of the restriction."""
+    G, O = pair(name)
+    Nf, Nc = 2 ** lam, 2 ** (lam - 1)
+    op = ts.Operator(G, lam, method=ts.TS_LSQP, q=2)
+    rf = inputs.uniform(O.num_unique(Nf), 50)
+    rf[O.dirichlet_mask(Nf)] = 0
+    rco = O.restrict(Nf, rf)
+    rcb = G.zeros(lam - 1)
+    ts.ts_restrict(op.h, lam, ts.TS_F64, G.to_block(lam, rf), rcb)
+    assert rel(rcb.cpu().numpy(), block_of(O, Nc, rco)) < TOL
+    del rf, rco, rcb
+    uc = inputs.uniform(O.num_unique(Nc), 51)
+    ufo = O.prolongate(Nf, uc)
+    base = inputs.uniform(O.num_unique(Nf), 52)
+    ufb = G.to_block(lam, base)
+    ts.ts_prolongate_add(op.h, lam, ts.TS_F64, G.to_block(lam - 1, uc), ufb)
+    base[O.dirichlet_mask(Nf)] = 0
+    assert rel(ufb.cpu().numpy(), block_of(O, Nf, base + ufo)) < TOL
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_load_vector_level8(ts, kind):
+    """The two-pass load vector (f once per slot, then the mass rows) against
+    the oracle's on every entry, one macro at level 8."""
+    G, O = pair("single")
+    lam, N = 8, 256
+    params = [0.55, 1.0] if kind == 0 else list(inputs.gaussian_bumps(3, 0.55))
+    fo = O.rhs(N, kind, params)
+    fb = G.rhs(lam, kind, params).cpu().numpy()
+    assert rel(fb, block_of(O, N, fo)) < TOL

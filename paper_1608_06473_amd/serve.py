@@ -27,8 +27,10 @@ same alone and in the mix.
 """
 from __future__ import annotations
 
+import argparse
 import collections
 import concurrent.futures as cf
+import json
 import threading
 import time
 
@@ -316,3 +318,35 @@ def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
         "wall_s": round(t_end, 3),
         "by_level": by_level,
     }
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Serve a Poisson trace of shell solves on one GPU "
+                                             "and print the latency / throughput summary.")
+    ap.add_argument("--requests", type=int, default=30)
+    ap.add_argument("--rate", type=float, default=50.0, help="arrivals per second")
+    ap.add_argument("--levels", default="4-7", help="uniform over this range")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--topology", default="shell288", choices=sorted(TOPOLOGIES))
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16w"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--inflight-work", type=float, default=2.0)
+    ap.add_argument("--max-active", type=int, default=32)
+    args = ap.parse_args()
+    from . import TS_F16W
+    lo, hi = (int(v) for v in args.levels.split("-"))
+    prec = {"f64": TS_F64, "f32": TS_F32, "f16w": TS_F16W}[args.precision]
+    trace = inputs.serving_trace(args.requests, rate=args.rate, seed=args.seed,
+                                 levels=tuple(range(lo, hi + 1)))
+    srv = Server(topology=args.topology, precision=prec, rtol=args.rtol,
+                 max_active=args.max_active, inflight_work=args.inflight_work,
+                 warm_levels=tuple(range(lo, hi + 1)))
+    try:
+        _, summ = srv.run(trace)
+    finally:
+        srv.close()
+    print(json.dumps(summ), flush=True)
+
+
+if __name__ == "__main__":
+    main()

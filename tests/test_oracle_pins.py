@@ -401,6 +401,30 @@ def test_volume_colouring_is_proper(orc):
 
 
 # --------------------------------------------------------------------------
+# load vector (Sec. 2.2 eq. algebraic): consistent mass matrix on the
+# nodal interpolant
+# --------------------------------------------------------------------------
+
+def test_load_vector_closed_forms_on_affine_macro(orc):
+    # Phi = Id, f = 1: row I of M 1 is the integral of the hat function,
+    # sum over its 24 fine tets of |T|/4; all N^3 fine tets of a macro have
+    # volume |macro| / N^3, so every interior row is 6 |macro| / N^3.  One
+    # Gaussian bump so wide that it is constant (to 1e-12) must give its
+    # amplitude times that: records are (cx, cy, cz, sigma, amplitude).
+    v, t = inputs.single_macro()
+    M = orc.Mesh(v, t, affine=True)
+    vol = abs(np.linalg.det(np.array([v[1] - v[0], v[2] - v[0], v[3] - v[0]]))) / 6.0
+    for N in (8, 16):
+        n_low = M.nv + M.ne * (N - 1) + M.nf * (N - 1) * (N - 2) // 2
+        expect = 6.0 * vol / N ** 3
+        f1 = M.rhs(N, 2)[n_low:]
+        assert f1.size == (N - 1) * (N - 2) * (N - 3) // 6
+        assert np.abs(f1 - expect).max() < 1e-14 * expect * 10
+        fb = M.rhs(N, 1, [0.3, 0.2, 0.1, 1e6, 2.5])[n_low:]
+        assert np.abs(fb - 2.5 * expect).max() < 1e-11 * expect
+
+
+# --------------------------------------------------------------------------
 # solver (Sec. 4.1): V-cycle, coarse solve and O(h^2) convergence
 # --------------------------------------------------------------------------
 

@@ -277,8 +277,9 @@ int ts_solve_step(ts_solver *sv);
 int ts_solve_query(ts_solver *sv, int *state, ts_solve_info *info);
 /* The batched step of a request loop: one outer iteration on each of the n
  * distinct solvers v[0..n-1], enqueued in the order given (the loop's
- * priority order).  Every solver must be TS_SOLVE_READY; otherwise nothing
- * is enqueued and TS_EINVAL is returned.  Each solver's launches go to its
+ * priority order).  Every solver must be TS_SOLVE_READY as ts_solve_query
+ * last reported it (as for ts_solve_step); otherwise nothing is enqueued and
+ * TS_EINVAL is returned.  Each solver's launches go to its
  * own stream: requests carry their own meshes and coefficients, so no
  * launch spans two of them, and the hardware queues overlap the streams.
  * A HIP error part-way returns TS_EHIP with the solvers before the failing

@@ -88,3 +88,38 @@ def test_level7_shell288_sampled_rows(ts):
     # the Dirichlet rows are zero
     mask = O.dirichlet_mask(N)
     assert not np.any(yc[mask])
+
+
+def test_level7_fp16_weight_apply_sampled_volume_rows(ts):
+    """FP16 weight evaluation on the benchmark workload, on volume rows the
+    oracle evaluates one by one.  The column polynomials are evaluated in
+    half precision on coefficients scaled to order one (d0 + d1 z + d2 z^2
+    by Horner: the rounded coefficients, z and two roundings give at most
+    about 5 u_h of the weight's magnitude, u_h = 2^-11), and the row is a
+    15-term FP32 sum with |x| <= 1.  With the centre weight about the sum of
+    the others, the row error stays below 15 * 3 u_h max_w |s_w|."""
+    import oracle
+    G, O = pair("shell288")
+    lam, N = 7, 128
+    op = ts.Operator(G, lam, method=ts.TS_LSQP, q=2, sample_j=2)
+    c = O.fit(N, oracle.LSQP, 2, 2)
+    op.set_coeffs(lam, c)
+    x = inputs.uniform(O.num_unique(N), 0)
+    xb = G.to_block(lam, x).float()
+    y16 = G.to_canon(lam, op.apply(lam, xb, dt=ts.TS_F16W).double()).cpu().numpy()
+    del xb
+    rng = np.random.default_rng(16)
+    nodes = []
+    while len(nodes) < 3000:
+        t = int(rng.integers(0, O.nt))
+        i, j, k = (int(v) for v in rng.integers(1, N - 2, 3))
+        if i + j + k <= N - 1:
+            nodes.append((t, i, j, k))
+    rows = np.array([O.canon(N, *n) for n in nodes], dtype=np.int64)
+    yo = O.apply_rows(N, x, rows, kind=oracle.LSQP, q=2, coeffs=c)
+    smax = np.array([max(abs(oracle.poly_eval(2, N, c[t][w], i, j, k)) for w in range(15))
+                     for t, i, j, k in nodes])
+    ratio = np.abs(y16[rows] - yo) / (2.0 ** -11 * smax)
+    print("FP16-weight apply: max |y16 - y| / (u_h max|s|) = %.2f" % ratio.max())
+    assert ratio.max() <= 45.0
+    assert ratio.max() > 0.0  # the half-precision evaluation is in effect

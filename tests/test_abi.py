@@ -43,3 +43,20 @@ def test_invalid_arguments_are_rejected_without_gpu():
     with pytest.raises(ts.TSError) as e:
         ts.ts_op_create(ctypes.c_void_p(), 5, stream=0)
     assert e.value.code == ts.TS_EINVAL
+
+
+def test_batched_step_rejects_bad_batches_without_gpu():
+    # argument checks come before any device work: a negative count, a
+    # null array with a positive count, a null solver and a repeated solver
+    # are refused with TS_EINVAL; an empty batch is a no-op
+    import paper_1608_06473_amd as ts
+    L = ts.lib()
+    assert L.ts_solve_batch_step(None, 0) == ts.TS_OK
+    assert L.ts_solve_batch_step(None, -1) == ts.TS_EINVAL
+    assert L.ts_solve_batch_step(None, 2) == ts.TS_EINVAL
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.ts_solve_batch_step(arr, 2) == ts.TS_EINVAL
+    assert "twice" in ts.ts_last_error()
+    arr1 = (ctypes.c_void_p * 1)(None)
+    assert L.ts_solve_batch_step(arr1, 1) == ts.TS_EINVAL
+    assert "null solver" in ts.ts_last_error()

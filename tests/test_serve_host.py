@@ -1,0 +1,44 @@
+"""Host logic of the request loop (no GPU): the request trace and the
+admission estimate."""
+import numpy as np
+
+from paper_1608_06473_amd import inputs
+
+
+def test_serving_trace_is_seeded_and_shaped():
+    a = inputs.serving_trace(2000, rate=50.0, seed=3)
+    b = inputs.serving_trace(2000, rate=50.0, seed=3)
+    assert a == b
+    t = np.array([r["t"] for r in a])
+    assert np.all(np.diff(t) > 0) and t[0] > 0
+    # exponential gaps of mean 1/rate: the sample mean of 2000 gaps lies
+    # within 4 standard errors (each gap has standard deviation 1/rate)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 0.02) < 4 * 0.02 / np.sqrt(gaps.size)
+    assert {r["level"] for r in a} == {4, 5, 6, 7}
+    ri = np.array([r["r_in"] for r in a])
+    assert ri.min() >= 0.4 and ri.max() <= 0.7
+    assert [r["id"] for r in a] == list(range(2000))
+    assert inputs.serving_trace(5, seed=4) != inputs.serving_trace(5, seed=3)
+
+
+def test_admission_estimate_covers_the_vectors():
+    # the serve module imports the binding (ctypes only; no GPU call here)
+    from paper_1608_06473_amd import TS_F32, TS_F64
+    from paper_1608_06473_amd.serve import request_bytes
+
+    def slots(n_macros, lam):
+        N = 2 ** lam
+        return n_macros * (N + 1) * (N + 2) * (N + 3) // 6
+
+    for lam in (4, 5, 6, 7):
+        b32 = request_bytes(288, lam, TS_F32)
+        b64 = request_bytes(288, lam, TS_F64)
+        # at least f and u in FP64 and the outer residual at the finest level
+        assert b32 >= 24 * slots(288, lam) and b64 >= 24 * slots(288, lam)
+        assert b64 > b32
+        if lam > 4:
+            assert request_bytes(288, lam, TS_F32) > request_bytes(288, lam - 1, TS_F32)
+    # a level-7 request of the 288-macro shell is a few GB, far below one
+    # GPU's 288 GB
+    assert 2e9 < request_bytes(288, 7, TS_F32) < 2e10

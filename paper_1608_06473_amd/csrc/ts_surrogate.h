@@ -17,6 +17,10 @@
 #include "ts_face.h"
 #include "ts_internal.h"
 
+#ifndef TS_GS_G
+#define TS_GS_G 3
+#endif
+
 namespace ts {
 
 template <int Q>
@@ -336,8 +340,10 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     wp.init_from(coef_f, coef_d, macro, N, i, j);
 
     // G planes are staged per barrier into one half of 2G plane buffers; a
-    // buffer is rewritten two groups later, after the next group's barrier
-    constexpr int G = TS_VOL_G;
+    // buffer is rewritten two groups later, after the next group's barrier.
+    // The smoother, which computes on a quarter of the planes, takes larger
+    // groups (fewer barriers); the apply and residual are faster with 2.
+    constexpr int G = MODE == 2 ? TS_GS_G : TS_VOL_G;
     __shared__ T buf[2 * G][KPT * VOL_THREADS];
     const size_t base = (size_t)macro * B;
     const int64_t bbytes = B * (int64_t)sizeof(T);

@@ -16,7 +16,7 @@ cycles under FP64 refinement, a bounded run of the serve loop, and the CPU
 oracle timed on the free rows of the same operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--level 7] [--mesh shell288] [--only-volume] [--no-solve] [--no-serve]
+       [--level 7] [--mesh shell288] [--only-volume] [--only-gs] [--no-solve] [--no-serve]
        [--serve-requests 30]
 """
 from __future__ import annotations
@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-volume", action="store_true",
                     help="time only the surrogate volume kernel (profiling runs)")
+    ap.add_argument("--only-gs", action="store_true",
+                    help="time only the FP64 Gauss-Seidel sweep (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-solve", action="store_true")
@@ -242,6 +244,13 @@ def main():
     log("volume kernel: %.3f ms, %.1f GB/s algorithmic (%.1f GDoF/s)"
         % (vol_ms, achieved, info.n_volume / vol_ms / 1e6))
     if args.only_volume:
+        return
+    if args.only_gs:
+        fb = G.rhs(lam, ts.TS_RHS_MANUFACTURED, [0.55, 1.0])
+        ub = xb.clone()
+        gs_ms = time_events(lambda: ts.ts_smooth(op.h, lam, ts.TS_F64, fb, ub, 1, stream), 3,
+                            stream)
+        log("GS sweep (FP64): %.3f ms" % gs_ms)
         return
 
     extra = {}

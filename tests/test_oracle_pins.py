@@ -72,6 +72,103 @@ def test_shell_free_dofs(orc, N, free36, free288):
 
 
 # --------------------------------------------------------------------------
+# blending map (Sec. 2.2): refined boundary nodes on the spheres, interior
+# macros in spherical layers, macro vertices fixed, Phi continuous, nested
+# node sets, (Phi - Id) o Psi = O(H^2)
+# --------------------------------------------------------------------------
+
+def _radii_counts(M, N, radii, tol=1e-14):
+    r = np.linalg.norm(M.coords(N), axis=1)
+    return [int((np.abs(r - rr) < tol).sum()) for rr in radii], r
+
+
+def _sphere_node_count(n_split, N):
+    # nodes of the level-N refinement of one cubed-sphere surface split
+    # n_split x n_split per cube face, each quad cut into two triangles
+    # (Euler: V - E + F = 2 with F = 12 n^2 triangles, E = 3F/2)
+    F = 12 * n_split ** 2
+    E = 3 * F // 2
+    V = 2 + E - F
+    return V + E * (N - 1) + F * (N - 1) * (N - 2) // 2
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_blending_boundary_and_layer_nodes_on_spheres(orc, N):
+    # Sec. 2.2: all refined nodes are projected onto the spherical surface,
+    # and the interior macros are mapped as well so that they form spherical
+    # layers.  On the 288-macro shell (radii 0.55, 0.775, 1) each of the
+    # three spheres carries exactly the nodes of its triangulated surface;
+    # mapping only the boundary nodes would leave the middle sphere with its
+    # 26 vertices alone.
+    M = orc.Mesh(*inputs.shell288())
+    cnt, r = _radii_counts(M, N, (0.55, 0.775, 1.0))
+    assert cnt == [_sphere_node_count(2, N)] * 3
+    # every Dirichlet node lies on one of the two boundary spheres
+    dm = M.dirichlet_mask(N)
+    on_b = (np.abs(r - 0.55) < 1e-14) | (np.abs(r - 1.0) < 1e-14)
+    assert np.array_equal(dm, on_b)
+    # the shell is covered: no node outside [r_in, r_out]
+    assert r.min() > 0.55 - 1e-14 and r.max() < 1.0 + 1e-14
+
+
+def test_blending_vertices_fixed_and_continuous(orc):
+    # Sec. 2.2: the macro vertices are vertices of every refined mesh and stay
+    # where they are; Phi is globally continuous, so every copy of a node
+    # shared by several macros maps to the same point
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t)
+    N = 8
+    corners = [(0, 0, 0), (N, 0, 0), (0, N, 0), (0, 0, N)]
+    for m in range(0, len(t), 5):
+        for a, c in enumerate(corners):
+            assert np.abs(M.node_xyz(N, m, *c) - v[t[m, a]]).max() < 1e-15
+    xyz = M.coords(N)
+    nu = M.num_unique(N)
+    checked = 0
+    for u in range(0, nu, 37):
+        cps = M.copies(N, u)
+        for (m, ijk) in cps:
+            assert np.abs(M.node_xyz(N, m, *ijk) - xyz[u]).max() < 1e-15
+        checked += len(cps) > 1
+    assert checked > 50
+
+
+def test_blending_nodes_are_nested(orc):
+    # Sec. 2.2: the vertices of level l are vertices of level l + 1, i.e.
+    # fine node (i, j, k) at N intervals is node (2i, 2j, 2k) at 2N
+    M = orc.Mesh(*inputs.shell288())
+    rng = np.random.default_rng(5)
+    N = 8
+    for _ in range(200):
+        m = int(rng.integers(0, M.nt))
+        i, j = rng.integers(0, N + 1, size=2)
+        k = int(rng.integers(0, N + 1 - min(N, i + j))) if i + j <= N else 0
+        if i + j + k > N:
+            continue
+        a = M.node_xyz(N, m, int(i), int(j), k)
+        b = M.node_xyz(2 * N, m, 2 * int(i), 2 * int(j), 2 * k)
+        assert np.abs(a - b).max() < 1e-15
+
+
+def test_blending_deviation_is_order_H2(orc):
+    # Sec. 2.2: ||(Phi_T - Id) o Psi_T||_inf = O(H^2).  On cubed-sphere shells
+    # split n x n per cube face and into n radial layers (n = 2, 4, 8), the
+    # largest distance between a mapped node and its affine position falls
+    # like the square of the longest macro edge H.
+    H, dev = [], []
+    for n in (2, 4, 8):
+        v, t = inputs.cubed_shell(n, tuple(0.55 + 0.45 * q / n for q in range(n + 1)))
+        e = v[t[:, [0, 0, 0, 1, 1, 2]]] - v[t[:, [1, 2, 3, 2, 3, 3]]]
+        H.append(np.linalg.norm(e, axis=2).max())
+        Ms = orc.Mesh(v, t)
+        Ma = orc.Mesh(v, t, affine=True)
+        dev.append(np.linalg.norm(Ms.coords(4) - Ma.coords(4), axis=1).max())
+    for a in range(2):
+        p = np.log(dev[a] / dev[a + 1]) / np.log(H[a] / H[a + 1])
+        assert 1.9 < p < 2.2, (H, dev, p)
+
+
+# --------------------------------------------------------------------------
 # fine tiling (Sec. 2.3, Sec. 4.2.1 incidence counts)
 # --------------------------------------------------------------------------
 
@@ -212,7 +309,6 @@ def test_ifem_operator_vs_global_assembly(orc, mesh, N):
     assert worst == 0.0
     dm = M.dirichlet_mask(N)
     db = B.dirichlet[B.slot_node]
-    assert np.array_equal(M.canon_to_block(N, dm.astype(float)) > 0, db) or True
     ids = M.block_canon_ids(N)
     assert np.array_equal(dm[ids], db)
 
@@ -235,6 +331,55 @@ def test_fit_recovers_polynomial_fields(orc):
         for p in [(1, 1, 1), (N - 3, 1, 1), (3, 5, 7)]:
             for w in (0, 7, 14):
                 assert abs(orc.poly_eval(q, N, c[w], *p) - orc.poly_eval(q, N, a[w], *p)) < 1e-10
+
+
+def test_fit_recovers_raw_power_fields(orc):
+    # The fit spans every polynomial of total degree <= q (Sec. 3.1, eq.
+    # numPolyCoeffs), whatever basis it is written in: a field built in raw
+    # powers (i/N)^a (j/N)^b (k/N)^c, a + b + c <= q, is recovered exactly at
+    # any node.  A basis missing or repeating a monomial fails this.
+    rng = np.random.default_rng(11)
+    for q, N, j in [(1, 16, 2), (2, 32, 2), (3, 32, 2), (4, 32, 2), (4, 64, 1)]:
+        exps = [(a, b, c) for a in range(q + 1) for b in range(q + 1) for c in range(q + 1)
+                if a + b + c <= q]
+        assert len(exps) == orc.num_coeffs(q)
+        g = rng.uniform(-1, 1, size=(15, len(exps)))
+
+        def field(p):
+            x, y, z = p[0] / N, p[1] / N, p[2] / N
+            mono = np.array([x ** a * y ** b * z ** c for (a, b, c) in exps])
+            return g @ mono
+
+        pts = orc.sample_points(N, orc.LSQP, j)
+        vals = np.array([field(p) for p in pts])
+        c = orc.fit_values(N, vals, orc.LSQP, q, j)
+        for p in [(1, 1, 1), (N - 3, 1, 1), (1, N - 3, 1), (1, 1, N - 3), (3, 5, 7),
+                  (N // 4, N // 3, N // 5)]:
+            e = np.array([orc.poly_eval(q, N, c[w], *p) for w in range(15)])
+            assert np.abs(e - field(p)).max() < 1e-11, (q, N, p)
+
+
+def test_ipoly_points_are_shrunk_macro_corners_and_midpoints(orc):
+    # Sec. 3.1: IPOLY samples at the quadratic nodal interpolation points of
+    # the shrunk macro element, i.e. the four corners and six edge midpoints
+    # of the tetrahedron spanned by the macro's interior nodes (i, j, k >= 1,
+    # i + j + k <= N - 1).  The corners are found here as the extreme points
+    # of the interior node set, not from the printed formula.
+    for N in (8, 16, 32, 128):
+        n = N
+        pts = np.array([(i, j, k) for k in range(1, n) for j in range(1, n) for i in range(1, n)
+                        if i + j + k <= n - 1])
+        corners = [tuple(pts[np.argmin(pts.sum(axis=1))])]
+        for ax in range(3):
+            corners.append(tuple(pts[np.argmax(pts[:, ax] * 4 - pts.sum(axis=1))]))
+        mids = [tuple((np.array(a) + np.array(b)) // 2) for ia, a in enumerate(corners)
+                for b in corners[ia + 1:]]
+        for a, ia in zip(corners, range(4)):
+            for b in corners[ia + 1:]:
+                assert all((x + y) % 2 == 0 for x, y in zip(a, b))  # midpoints are nodes
+        want = sorted(corners + mids)
+        got = sorted(tuple(int(v) for v in p) for p in orc.sample_points(N, orc.IPOLY))
+        assert got == want, (N, got, want)
 
 
 def test_ipoly_interpolates(orc):

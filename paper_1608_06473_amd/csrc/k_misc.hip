@@ -708,39 +708,53 @@ __global__ __launch_bounds__(256) void k_fit_gram(int N, int q, const int* __res
     for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) work[e] = G[e];
 }
 
-// per macro: rhs = A^T B_m, then (L L^T) a = rhs; coef[m][w][c]
+// per macro: rhs = A^T B_m, then (L L^T) a = rhs; then one step of
+// iterative refinement, rhs = A^T (B_m - A a) in FP64 and (L L^T) d = rhs,
+// a += d, so that the accuracy of a is no longer limited by the squared
+// condition number of the normal equations.  coef[m][w][c]
 __global__ __launch_bounds__(256) void k_fit_solve(int N, int q, const int* __restrict__ pts, int npts,
                                                    const double* __restrict__ Bv, const double* __restrict__ Lf,
                                                    double* __restrict__ coef) {
     __shared__ double R[35 * NW];
+    __shared__ double Z[35 * NW];
     const int m = blockIdx.x;
     const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
     const double* Bm = Bv + (size_t)m * npts * NW;
+    for (int pass = 0; pass < 2; pass++) {
+        for (int e = threadIdx.x; e < mq * NW; e += blockDim.x) {
+            const int c = e / NW, w = e % NW;
+            double s = 0.0;
+            double row[35];
+            for (int p = 0; p < npts; p++) {
+                const int nb = basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
+                double b = Bm[(size_t)p * NW + w];
+                if (pass == 1)
+                    for (int c2 = 0; c2 < nb; c2++) b -= row[c2] * Z[c2 * NW + w];
+                s += row[c] * b;
+            }
+            R[c * NW + w] = s;
+        }
+        __syncthreads();
+        const int w = threadIdx.x;
+        if (w < NW) {
+            double z[35];
+            for (int ii = 0; ii < mq; ii++) {
+                double t = R[ii * NW + w];
+                for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
+                z[ii] = t / Lf[ii * mq + ii];
+            }
+            for (int ii = mq - 1; ii >= 0; ii--) {
+                double t = z[ii];
+                for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
+                z[ii] = t / Lf[ii * mq + ii];
+            }
+            for (int c = 0; c < mq; c++) Z[c * NW + w] = pass == 0 ? z[c] : Z[c * NW + w] + z[c];
+        }
+        __syncthreads();
+    }
     for (int e = threadIdx.x; e < mq * NW; e += blockDim.x) {
         const int c = e / NW, w = e % NW;
-        double s = 0.0;
-        double row[35];
-        for (int p = 0; p < npts; p++) {
-            basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
-            s += row[c] * Bm[(size_t)p * NW + w];
-        }
-        R[c * NW + w] = s;
-    }
-    __syncthreads();
-    const int w = threadIdx.x;
-    if (w < NW) {
-        double z[35];
-        for (int ii = 0; ii < mq; ii++) {
-            double t = R[ii * NW + w];
-            for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
-            z[ii] = t / Lf[ii * mq + ii];
-        }
-        for (int ii = mq - 1; ii >= 0; ii--) {
-            double t = z[ii];
-            for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
-            z[ii] = t / Lf[ii * mq + ii];
-        }
-        for (int c = 0; c < mq; c++) coef[((size_t)m * NW + w) * mq + c] = z[c];
+        coef[((size_t)m * NW + w) * mq + c] = Z[c * NW + w];
     }
 }
 
@@ -765,32 +779,43 @@ __global__ __launch_bounds__(64) void k_fit_solve_pair(int N2, int q, const int*
                                                        int wo, int p,
                                                        double* __restrict__ coef7) {
     __shared__ double R[35];
+    __shared__ double Z[35];
     const int m = blockIdx.x;
     const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
     const double* Bm = Bv + (size_t)m * np * NW;
-    for (int c = threadIdx.x; c < mq; c += blockDim.x) {
-        double sum = 0.0;
-        double row[35];
-        for (int t = 0; t < 2 * np; t++) {
-            basis_row(q, N2, pts2[3 * t], pts2[3 * t + 1], pts2[3 * t + 2], row);
-            sum += row[c] * Bm[(size_t)(t < np ? t : t - np) * NW + (t < np ? w : wo)];
+    // normal equations, then one step of iterative refinement on the FP64
+    // residual (as in k_fit_solve)
+    for (int pass = 0; pass < 2; pass++) {
+        for (int c = threadIdx.x; c < mq; c += blockDim.x) {
+            double sum = 0.0;
+            double row[35];
+            for (int t = 0; t < 2 * np; t++) {
+                const int nb = basis_row(q, N2, pts2[3 * t], pts2[3 * t + 1], pts2[3 * t + 2], row);
+                double b = Bm[(size_t)(t < np ? t : t - np) * NW + (t < np ? w : wo)];
+                if (pass == 1)
+                    for (int c2 = 0; c2 < nb; c2++) b -= row[c2] * Z[c2];
+                sum += row[c] * b;
+            }
+            R[c] = sum;
         }
-        R[c] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double z[35];
+            for (int ii = 0; ii < mq; ii++) {
+                double t = R[ii];
+                for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
+                z[ii] = t / Lf[ii * mq + ii];
+            }
+            for (int ii = mq - 1; ii >= 0; ii--) {
+                double t = z[ii];
+                for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
+                z[ii] = t / Lf[ii * mq + ii];
+            }
+            for (int c = 0; c < mq; c++) Z[c] = pass == 0 ? z[c] : Z[c] + z[c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double z[35];
-    for (int ii = 0; ii < mq; ii++) {
-        double t = R[ii];
-        for (int kk = 0; kk < ii; kk++) t -= Lf[ii * mq + kk] * z[kk];
-        z[ii] = t / Lf[ii * mq + ii];
-    }
-    for (int ii = mq - 1; ii >= 0; ii--) {
-        double t = z[ii];
-        for (int kk = ii + 1; kk < mq; kk++) t -= Lf[kk * mq + ii] * z[kk];
-        z[ii] = t / Lf[ii * mq + ii];
-    }
-    for (int c = 0; c < mq; c++) coef7[((size_t)m * 7 + p) * mq + c] = z[c];
+    for (int c = threadIdx.x; c < mq; c += blockDim.x) coef7[((size_t)m * 7 + p) * mq + c] = Z[c];
 }
 
 __device__ __forceinline__ double binom_small(int n, int k) {

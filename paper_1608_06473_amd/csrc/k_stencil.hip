@@ -139,77 +139,92 @@ __global__ __launch_bounds__(256) void k_face_fit(const int4* __restrict__ cp,
             ec[p] = M2 + (e - NG) % NW;
         }
     }
-    double acc[PER];
+    // Pass 0 forms the normal equations and solves them; pass 1 forms A^T of
+    // the FP64 residual b - A x of that solution and adds the correction
+    // (one step of iterative refinement: the squared condition number of the
+    // normal equations no longer limits the accuracy of x).
+    for (int pass = 0; pass < 2; pass++) {
+        double acc[PER];
 #pragma unroll
-    for (int p = 0; p < PER; p++) acc[p] = 0.0;
-    for (int c0 = 0; c0 < ns; c0 += CH) {
-        const int sidx = c0 + tid;
-        if (tid < CH && sidx < ns) {
-            int bq = 1, r = sidx;
-            while (r >= Ns - 1 - bq) {
-                r -= Ns - 1 - bq;
-                bq++;
+        for (int p = 0; p < PER; p++) acc[p] = 0.0;
+        for (int c0 = 0; c0 < ns; c0 += CH) {
+            const int sidx = c0 + tid;
+            if (tid < CH && sidx < ns) {
+                int bq = 1, r = sidx;
+                while (r >= Ns - 1 - bq) {
+                    r -= Ns - 1 - bq;
+                    bq++;
+                }
+                const int a = (r + 1) * st, b = bq * st;
+                const int q = off + (b - 1) * (N - 1) - (b - 1) * b / 2 + a - 1;
+                const int4 ca = cp[q];
+                const int fa = face_type(N, ca.y, ca.z, ca.w);
+                const double invN = 1.0 / (double)N;
+                const double u = (double)(fa == 0 ? ca.z : ca.y) * invN - 1.0 / 3.0;
+                const double v = (double)(fa <= 1 ? ca.w : ca.z) * invN - 1.0 / 3.0;
+                double phi[M2];
+                face_phi<FQ>(u, v, phi);
+#pragma unroll
+                for (int c = 0; c < M2; c++) sphi[tid][c] = phi[c];
+                for (int e = 0; e < NW; e++) {
+                    double bv = sten[(size_t)e * n2 + q];
+                    if (pass == 1)
+                        for (int c = 0; c < M2; c++) bv -= phi[c] * X[c][e];
+                    sw[tid][e] = bv;
+                }
             }
-            const int a = (r + 1) * st, b = bq * st;
-            const int q = off + (b - 1) * (N - 1) - (b - 1) * b / 2 + a - 1;
-            const int4 ca = cp[q];
-            const int fa = face_type(N, ca.y, ca.z, ca.w);
-            const double invN = 1.0 / (double)N;
-            const double u = (double)(fa == 0 ? ca.z : ca.y) * invN - 1.0 / 3.0;
-            const double v = (double)(fa <= 1 ? ca.w : ca.z) * invN - 1.0 / 3.0;
-            double phi[M2];
-            face_phi<FQ>(u, v, phi);
+            __syncthreads();
+            const int nc = min(CH, ns - c0);
 #pragma unroll
-            for (int c = 0; c < M2; c++) sphi[tid][c] = phi[c];
-#pragma unroll
-            for (int e = 0; e < NW; e++) sw[tid][e] = sten[(size_t)e * n2 + q];
+            for (int p = 0; p < PER; p++) {
+                if (er[p] < 0 || (pass == 1 && ec[p] < M2)) continue;
+                double a = acc[p];
+                for (int k = 0; k < nc; k++)
+                    a += sphi[k][er[p]] * (ec[p] < M2 ? sphi[k][ec[p]] : sw[k][ec[p] - M2]);
+                acc[p] = a;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const int nc = min(CH, ns - c0);
 #pragma unroll
-        for (int p = 0; p < PER; p++) {
-            if (er[p] < 0) continue;
-            double a = acc[p];
-            for (int k = 0; k < nc; k++)
-                a += sphi[k][er[p]] * (ec[p] < M2 ? sphi[k][ec[p]] : sw[k][ec[p] - M2]);
-            acc[p] = a;
+        for (int p = 0; p < PER; p++)
+            if (er[p] >= 0) sys[tid + p * 256] = acc[p];
+        __syncthreads();
+        if (tid == 0) {
+            if (pass == 0) {
+                // Gram G (upper triangle, row-packed) -> Cholesky G = R^T R
+                for (int r = 0, e = 0; r < M2; r++)
+                    for (int c = r; c < M2; c++, e++) R[r][c] = sys[e];
+                for (int r = 0; r < M2; r++) {
+                    double d = R[r][r];
+                    for (int k = 0; k < r; k++) d -= R[k][r] * R[k][r];
+                    d = sqrt(d);
+                    R[r][r] = d;
+                    for (int c = r + 1; c < M2; c++) {
+                        double v = R[r][c];
+                        for (int k = 0; k < r; k++) v -= R[k][r] * R[k][c];
+                        R[r][c] = v / d;
+                    }
+                }
+            }
+            // R^T z = rhs, then R dx = z, for the 15 entries; x (+)= dx
+            for (int w = 0; w < NW; w++) {
+                double z[M2];
+                for (int r = 0; r < M2; r++) {
+                    double v = sys[NG + r * NW + w];
+                    for (int k = 0; k < r; k++) v -= R[k][r] * z[k];
+                    z[r] = v / R[r][r];
+                }
+                for (int r = M2 - 1; r >= 0; r--) {
+                    double v = z[r];
+                    for (int k = r + 1; k < M2; k++) v -= R[r][k] * z[k];
+                    z[r] = v / R[r][r];
+                }
+                for (int r = 0; r < M2; r++) X[r][w] = pass == 0 ? z[r] : X[r][w] + z[r];
+            }
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int p = 0; p < PER; p++)
-        if (er[p] >= 0) sys[tid + p * 256] = acc[p];
-    __syncthreads();
     if (tid != 0) return;
-    // Gram G (upper triangle, row-packed) -> Cholesky G = R^T R in place
-    for (int r = 0, e = 0; r < M2; r++)
-        for (int c = r; c < M2; c++, e++) R[r][c] = sys[e];
-    for (int r = 0; r < M2; r++)
-        for (int w = 0; w < NW; w++) X[r][w] = sys[NG + r * NW + w];
-    for (int r = 0; r < M2; r++) {
-        double d = R[r][r];
-        for (int k = 0; k < r; k++) d -= R[k][r] * R[k][r];
-        d = sqrt(d);
-        R[r][r] = d;
-        for (int c = r + 1; c < M2; c++) {
-            double v = R[r][c];
-            for (int k = 0; k < r; k++) v -= R[k][r] * R[k][c];
-            R[r][c] = v / d;
-        }
-    }
-    // R^T z = rhs, then R x = z, for the 15 entries
-    for (int w = 0; w < NW; w++) {
-        for (int r = 0; r < M2; r++) {
-            double v = X[r][w];
-            for (int k = 0; k < r; k++) v -= R[k][r] * X[k][w];
-            X[r][w] = v / R[r][r];
-        }
-        for (int r = M2 - 1; r >= 0; r--) {
-            double v = X[r][w];
-            for (int k = r + 1; k < M2; k++) v -= R[r][k] * X[k][w];
-            X[r][w] = v / R[r][r];
-        }
-    }
     const int4 c0 = cp[off];
     double* out = fcoef + ((size_t)c0.x * 4 + face_type(N, c0.y, c0.z, c0.w)) * (NW * M2);
     for (int w = 0; w < NW; w++)

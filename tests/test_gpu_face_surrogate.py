@@ -2,11 +2,11 @@
 
 The volume coefficients are the oracle's (imported), so the volume rows are
 the same operator on both sides; each side fits its own face polynomials
-(GPU: FP64 normal equations in the first macro's face coordinates, oracle:
-Householder QR in the face frame), the same function up to rounding.  As for
-the volume's own fits, the weights agree to 1e-12 (q = 2) and 1e-10 (q = 4)
-relative to the largest weight, and an output sums 15 weighted inputs
-|x| <= 1: bounds 1.5e-11 and 1.5e-9 on the operator.
+(GPU: FP64 normal equations in the first macro's face coordinates with one
+step of iterative refinement on the FP64 residual, oracle: Householder QR in
+the face frame), the same least-squares function up to rounding, so the
+operators meet the 1e-12 bound of the applies (measured on MI355X:
+1.1e-15 .. 1.6e-14, q = 2 and q = 4).
 """
 import numpy as np
 import pytest
@@ -19,7 +19,8 @@ from paper_1608_06473_amd import inputs  # noqa: E402
 
 from test_gpu_parity import block_of, pair, rel, share_fits  # noqa: E402
 
-OWN = {2: 1.5e-11, 4: 1.5e-9}
+OWN = {2: 1e-12, 4: 1e-12}
+GS2 = 1e-11  # two Gauss-Seidel sweeps: the apply bound per operation, composed
 
 
 @pytest.fixture(scope="module")
@@ -80,7 +81,7 @@ def test_gauss_seidel_sweep(ts, dt):
     fb = G.to_block(lam, f)
     if dt == 0:
         op.smooth(lam, fb, ub, sweeps=2)
-        assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < OWN[2]
+        assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < GS2
     else:  # FP32 vectors, FP64 face-row evaluation
         u32 = ub.float()
         op.smooth(lam, fb.float(), u32, sweeps=2, dt=ts.TS_F32)

@@ -98,8 +98,10 @@ def test_surrogate_coefficients(ts, name, lam, method, q, j):
     op = ts.Operator(G, lam, method=method, q=q, sample_j=j)
     cg = op.coeffs(lam)
     co = O.fit(N, method, q, j)
-    # normal equations (GPU) vs Householder QR (oracle): compare the weights
-    # they produce, which is what the operator uses
+    # normal equations with one FP64 refinement step (GPU) vs Householder QR
+    # (oracle): compare the weights they produce, which is what the operator
+    # uses.  Measured on MI355X: 1.8e-15 .. 1.2e-13 relative to the largest
+    # weight (the largest for q = 4 interpolation, j = 1)
     pts = [(1, 1, 1), (N // 4, N // 4, N // 4), (N - 3, 1, 1), (2, 3, 5)]
     import oracle
     scale = 0.0
@@ -111,7 +113,7 @@ def test_surrogate_coefficients(ts, name, lam, method, q, j):
                 b = oracle.poly_eval(q, N, co[t, w], *p)
                 err = max(err, abs(a - b))
                 scale = max(scale, abs(b))
-    assert err / scale < (1e-12 if q == 2 else 1e-10)
+    assert err / scale < TOL, err / scale
 
 
 # ---------------------------------------------------------------- operator
@@ -153,14 +155,15 @@ def test_apply_surrogate_shared_coefficients(ts, name, lam):
     assert _apply_case(ts, name, lam, ts.TS_LSQP, 2, shared=True) < TOL
 
 
-# Each side fits on its own (GPU: FP64 normal equations, oracle: Householder
-# QR).  The weights agree to 1e-12 (q = 2) and 1e-10 (q = 4) relative to the
-# largest weight; an output sums 15 weighted inputs |x| <= 1, so the bound on
-# the operator is 15 times that.
+# Each side fits on its own (GPU: FP64 normal equations and one step of
+# iterative refinement on the FP64 residual, oracle: Householder QR); both
+# reach the least-squares solution to rounding, so the operators meet the
+# same 1e-12 bound as with shared coefficients (measured on MI355X:
+# 4.0e-15 .. 2.9e-14 over these cases, q = 2 and q = 4 alike).
 @pytest.mark.parametrize("name,lam,q", [("single", 5, 2), ("shell288", 4, 2), ("shell288", 4, 4),
-                                        ("shell36", 5, 2)])
+                                        ("shell36", 5, 2), ("shell288", 5, 4)])
 def test_apply_surrogate_own_fits(ts, name, lam, q):
-    assert _apply_case(ts, name, lam, ts.TS_LSQP, q, shared=False) < (1.5e-11 if q < 4 else 1.5e-9)
+    assert _apply_case(ts, name, lam, ts.TS_LSQP, q, shared=False) < TOL
 
 
 def test_apply_ipoly_and_rowsum_centre(ts):

@@ -2,11 +2,11 @@
 through the C ABI vs the oracle.
 
 Each side fits on its own (GPU: FP64 normal equations of the seven pair
-polynomials, translated on the device into the 15 per-direction polynomials
-of the volume kernel; oracle: Householder QR of the pair polynomials,
-evaluated at the edge midpoints).  As for the other own fits the weights
-agree to 1e-12 (q = 2) and 1e-10 (q = 4) relative to the largest weight:
-bounds 1.5e-11 and 1.5e-9 on the operator.
+polynomials with one step of iterative refinement on the FP64 residual,
+translated on the device into the 15 per-direction polynomials of the volume
+kernel; oracle: Householder QR of the pair polynomials, evaluated at the edge
+midpoints): the operators meet the 1e-12 bound of the applies (measured on
+MI355X: 3.4e-15 .. 2.6e-14, q = 2 and q = 4).
 """
 import numpy as np
 import pytest
@@ -19,7 +19,8 @@ from paper_1608_06473_amd import inputs  # noqa: E402
 
 from test_gpu_parity import block_of, pair, rel  # noqa: E402
 
-OWN = {2: 1.5e-11, 4: 1.5e-9}
+OWN = {2: 1e-12, 4: 1e-12}
+GS2 = 1e-11  # two Gauss-Seidel sweeps: the apply bound per operation, composed
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +62,7 @@ def test_gauss_seidel_and_vcycle(ts):
                     kind=oracle.SYM, q=2, coeffs=cs[-1])
     ub = G.to_block(lam, u)
     op.smooth(lam, G.to_block(lam, f), ub, sweeps=2)
-    assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < OWN[2]
+    assert rel(ub.cpu().numpy(), block_of(O, N, uo)) < GS2
     fm = O.rhs(N, 0, [0.55, 1.0])
     u0 = inputs.uniform(nu, 12) * 1e-3
     mg = oracle.Multigrid(O, 2, lam, kind=oracle.SYM, q=2, coeffs=cs)

@@ -242,10 +242,14 @@ int ts_prolongate_add(ts_op *op, int level, int dtype, const void *uc, void *uf,
  * deterministic (fixed reduction order). */
 int ts_norm2(ts_mesh *mesh, int level, int dtype, const void *x, double *out, ts_stream s);
 
-/* ---- multigrid (Sec. 4.1: V(3,3) with Gauss-Seidel smoothing) -----------
+/* ---- multigrid (Sec. 4 introduction: V(3,3) with Gauss-Seidel smoothing) --
  * Coarsest level 2 is solved exactly in FP64 with the inverse of its IFEM
  * matrix (computed on the device at creation).  Workspace owned by the
- * solver. */
+ * solver, all of it allocated by ts_solver_create (per-level cycle vectors of
+ * the solve's precision, the outer residual and correction, stored interface
+ * rows).  TS_EINVAL above level 8 if the solve would need element-wise
+ * volume rows there (dd, a TS_IFEM operator, or macros the selective
+ * surrogate keeps exact). */
 int ts_solver_create(ts_op *op, int level, const ts_solve_params *p, ts_solver **out);
 int ts_solver_destroy(ts_solver *sv);
 /* one V(nu1, nu2) cycle on L u = f at the solver's level, in place */
@@ -267,7 +271,10 @@ int ts_solve(ts_solver *sv, const double *f, double *u, ts_solve_info *info, ts_
  *     (info->status is final: TS_OK, TS_ENOCONV or TS_ENONFINITE); info
  *     (optional) gets the history so far;
  *   ts_solve_step enqueues one outer iteration on the stream given to
- *     ts_solve_begin (TS_EINVAL unless the state is TS_SOLVE_READY).
+ *     ts_solve_begin (TS_EINVAL unless the state is TS_SOLVE_READY).  A step
+ *     allocates nothing (ts_solver_create allocated every vector it uses);
+ *     if enqueuing fails part-way (TS_EHIP) the solve ends: TS_SOLVE_DONE
+ *     with info.status set to the error code.
  * f and u are the caller's device vectors and must stay valid until DONE; u
  * holds the initial guess.  Results are bitwise identical to ts_solve with
  * the same inputs.  One host thread at a time per solver (and per mesh). */
@@ -283,7 +290,10 @@ int ts_solve_query(ts_solver *sv, int *state, ts_solve_info *info);
  * own stream: requests carry their own meshes and coefficients, so no
  * launch spans two of them, and the hardware queues overlap the streams.
  * A HIP error part-way returns TS_EHIP with the solvers before the failing
- * one stepped (their state is then TS_SOLVE_RUNNING).  n = 0 is a no-op. */
+ * one stepped (their state is then TS_SOLVE_RUNNING); the failing solver's
+ * solve ends (TS_SOLVE_DONE, info.status = the error code, u holds a partly
+ * applied cycle) and the solvers after it are not stepped.  n = 0 is a
+ * no-op. */
 int ts_solve_batch_step(ts_solver *const *v, int n);
 
 /* device memory currently held by all meshes, operators and solvers of the

@@ -325,6 +325,25 @@ def dtype_torch(dt):
     return torch.float64 if dt == TS_F64 else torch.float32
 
 
+def check_vector(t, n, dt, what="vector"):
+    """Reject a tensor the library cannot take as a block vector of n entries
+    of dtype dt: wrong element type, not contiguous, wrong length, or not in
+    device memory (the kernels would read or write past the buffer).  Raises
+    TSError(TS_EINVAL) before any library call."""
+    want = dtype_torch(dt)
+    if getattr(t, "dtype", None) != want:
+        raise TSError(TS_EINVAL, "%s: dtype %s, expected %s" % (what, getattr(t, "dtype", type(t)),
+                                                                want))
+    if not t.is_contiguous():
+        raise TSError(TS_EINVAL, "%s: not contiguous" % what)
+    if t.numel() != n:
+        raise TSError(TS_EINVAL, "%s: %d entries, the level's block vector has %d"
+                      % (what, t.numel(), n))
+    if not t.is_cuda:
+        raise TSError(TS_EINVAL, "%s: not a device tensor" % what)
+    return t
+
+
 class Mesh:
     """Owning wrapper of a ts_mesh handle."""
 
@@ -415,19 +434,32 @@ class Operator:
     def set_coeffs(self, level, c):
         ts_op_coeffs_import(self.h, level, c)
 
+    def _n(self, level):
+        return self.mesh.layout(level).vec_len
+
     def apply(self, level, x, y=None, dt=TS_F64):
+        n = self._n(level)
+        check_vector(x, n, dt, "x")
         if y is None:
             y = self.mesh.zeros(level, dt)
+        check_vector(y, n, dt, "y")
         ts_apply(self.h, level, dt, x, y)
         return y
 
     def residual(self, level, f, u, r=None, dt=TS_F64):
+        n = self._n(level)
+        check_vector(f, n, dt, "f")
+        check_vector(u, n, dt, "u")
         if r is None:
             r = self.mesh.zeros(level, dt)
+        check_vector(r, n, dt, "r")
         ts_residual(self.h, level, dt, f, u, r)
         return r
 
     def smooth(self, level, f, u, sweeps=1, dt=TS_F64):
+        n = self._n(level)
+        check_vector(f, n, dt, "f")
+        check_vector(u, n, dt, "u")
         ts_smooth(self.h, level, dt, f, u, sweeps)
         return u
 
@@ -443,17 +475,29 @@ class Solver:
         self.level = level
         self.h = ts_solver_create(op.h, level, **kw)
 
+    def _n(self):
+        return self.op.mesh.layout(self.level).vec_len
+
     def vcycle(self, f, u, dt=TS_F64):
+        n = self._n()
+        check_vector(f, n, dt, "f")
+        check_vector(u, n, dt, "u")
         ts_vcycle(self.h, dt, f, u)
         return u
 
     def solve(self, f, u=None, raise_on_fail=True, stream=None):
+        n = self._n()
+        check_vector(f, n, TS_F64, "f")
         if u is None:
             u = self.op.mesh.zeros(self.level)
+        check_vector(u, n, TS_F64, "u")
         rc, info = ts_solve(self.h, f, u, stream=stream, raise_on_fail=raise_on_fail)
         return u, rc, info
 
     def begin(self, f, u, stream=None):
+        n = self._n()
+        check_vector(f, n, TS_F64, "f")
+        check_vector(u, n, TS_F64, "u")
         ts_solve_begin(self.h, f, u, stream)
 
     def step(self):

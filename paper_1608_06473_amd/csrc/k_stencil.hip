@@ -411,6 +411,15 @@ static const double* level_coords(Mesh& M, int lam, hipStream_t s) {
     return G.xyz.p;
 }
 
+// builds (once per geometry) what the operator's rows read on level lam: the
+// stored interface stencils and, if element-wise volume rows are needed
+// there, the stored coordinates
+void warm_level(const ts_op* op, int lam, bool ifem_rows, hipStream_t s) {
+    Mesh& M = op->mesh->m;
+    face_stencils(M, lam, s);
+    if (ifem_rows && M.level(lam).lds_kpt <= 4) level_coords(M, lam, s);
+}
+
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                         const void* f, int colour, hipStream_t s, const int* mlist, int n_list) {
     Mesh& M = op->mesh->m;

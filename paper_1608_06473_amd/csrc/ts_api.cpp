@@ -255,6 +255,24 @@ static X* vec(std::map<int, std::unique_ptr<DBuf<X>>>& m, int lam, int64_t n) {
     return b->p;
 }
 
+// the V-cycle vectors of every level below the solver's (restricted
+// right-hand side, correction) and of the levels above 2 (residual)
+static void alloc_cycle_vectors(ts_solver* sv, int vd) {
+    Mesh& M = sv->op->mesh->m;
+    for (int lam = sv->L; lam >= 3; lam--) {
+        const int64_t nf = M.level(lam).len, nc = M.level(lam - 1).len;
+        if (vd == TS_F64) {
+            vec(sv->r64, lam, nf);
+            vec(sv->f64, lam - 1, nc);
+            vec(sv->u64, lam - 1, nc);
+        } else {
+            vec(sv->r32, lam, nf);
+            vec(sv->f32, lam - 1, nc);
+            vec(sv->u32, lam - 1, nc);
+        }
+    }
+}
+
 static void coarse_setup(ts_solver* sv, hipStream_t s) {
     Mesh& M = sv->op->mesh->m;
     const int lam = 2;
@@ -650,6 +668,13 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
         check_dtype(p->precision);
         TS_REQUIRE(!p->dd || p->precision == TS_F64, TS_EINVAL,
                    "double discretisation runs in FP64 precision");
+        // element-wise volume rows stop at level 8: a solve above it must
+        // keep surrogate rows everywhere and take no exact residuals
+        for (int lam = 9; lam <= level; lam++) {
+            TS_REQUIRE(!p->dd, TS_EINVAL, "double discretisation needs IFEM rows: level 8 at most");
+            TS_REQUIRE(uses_surrogate(op, lam) && op->lv.at(lam)->n_ifem == 0, TS_EINVAL,
+                       "IFEM volume rows (method or selective surrogate) are supported up to level 8");
+        }
         auto* sv = new ts_solver();
         try {
             sv->op = op;
@@ -662,6 +687,14 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
             TS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
             try {
                 coarse_setup(sv, s);
+                // stored rows, coordinates and Gauss-Seidel scratch of every
+                // level the cycle visits, built now rather than in a step
+                for (int lam = 3; lam <= level; lam++) {
+                    const bool ifem = p->dd || !uses_surrogate(op, lam) || op->lv.at(lam)->n_ifem > 0;
+                    warm_level(op, lam, ifem, s);
+                    iface_tmp(op, lam);
+                }
+                TS_HIP(hipStreamSynchronize(s));
             } catch (...) {
                 (void)hipStreamDestroy(s);
                 throw;
@@ -670,6 +703,14 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
             Mesh& M = op->mesh->m;
             sv->partial.alloc(norm_partial_count(M, level));
             sv->nrm.alloc(3);
+            // every vector a solve step uses is allocated here, so that a step
+            // never allocates (and cannot fail part-way on memory)
+            alloc_cycle_vectors(sv, p->precision == TS_F64 ? TS_F64 : TS_F32);
+            sv->r_outer.alloc(M.level(level).len);
+            if (p->precision != TS_F64) {
+                sv->r_in.alloc(M.level(level).len);
+                sv->e_in.alloc(M.level(level).len);
+            }
             TS_HIP(hipHostMalloc((void**)&sv->hnrm, 3 * sizeof(double), hipHostMallocDefault));
             TS_HIP(hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming));
         } catch (...) {
@@ -831,10 +872,25 @@ int ts_solve_begin(ts_solver* sv, const double* f, double* u, ts_stream s) {
     });
 }
 
+// A step that fails part-way (a HIP error while enqueuing) leaves part of a
+// cycle applied to u: the solve ends there, DONE with the error's status.
+static void step_or_finish(ts_solver* sv) {
+    try {
+        solve_step(sv);
+    } catch (const Error& e) {
+        if (sv->state == TS_SOLVE_READY) {
+            sv->info.status = e.code;
+            sv->state = TS_SOLVE_DONE;
+        }
+        throw;
+    }
+}
+
 int ts_solve_step(ts_solver* sv) {
     return guarded([&] {
         TS_REQUIRE(sv, TS_EINVAL, "null solver");
-        solve_step(sv);
+        TS_REQUIRE(sv->state == TS_SOLVE_READY, TS_EINVAL, "the solver is not ready for a step");
+        step_or_finish(sv);
     });
 }
 
@@ -850,7 +906,7 @@ int ts_solve_batch_step(ts_solver* const* v, int n) {
             TS_REQUIRE(v[a]->state == TS_SOLVE_READY, TS_EINVAL,
                        "a solver in the batch is not ready for a step");
         }
-        for (int a = 0; a < n; a++) solve_step(v[a]);
+        for (int a = 0; a < n; a++) step_or_finish(v[a]);
     });
 }
 
@@ -871,7 +927,7 @@ int ts_solve(ts_solver* sv, const double* f, double* u, ts_solve_info* info, ts_
             TS_HIP(hipEventSynchronize(sv->ev));
             const int st = solve_query(sv);
             if (st == TS_SOLVE_DONE) break;
-            solve_step(sv);
+            step_or_finish(sv);
         }
         TS_HIP(hipEventSynchronize(sv->ev));
         *info = sv->info;

@@ -254,6 +254,7 @@ void build_topology(Mesh& M);
 // macro geometry records (host and device) from the vertex coordinates
 void build_geometry(Mesh& M);
 const double* face_stencils(Mesh& M, int lam, hipStream_t s);
+void warm_level(const ts_op* op, int lam, bool ifem_rows, hipStream_t s);
 
 // ------------------------------------------------------------ operators
 struct LevelOp {

@@ -36,9 +36,9 @@ import time
 
 import numpy as np
 
-from . import (TS_F32, TS_F64, TS_LSQP, TS_OK, TS_RHS_BUMPS, TS_SOLVE_DONE, TS_SOLVE_READY,
-               Mesh, Operator, Solver, inputs, ts_device_bytes, ts_solve_batch_step,
-               ts_solve_info)
+from . import (TS_EINVAL, TS_ENOMEM, TS_F32, TS_F64, TS_LSQP, TS_OK, TS_RHS_BUMPS,
+               TS_SOLVE_DONE, TS_SOLVE_READY, Mesh, Operator, Solver, TSError, inputs,
+               ts_device_bytes, ts_solve_batch_step, ts_solve_info)
 
 TOPOLOGIES = {
     # the 288-macro shell (faces split 2 x 2, two radial layers) scaled to the
@@ -161,9 +161,16 @@ class Server:
         r.status = r.info.status
         r.cycles = r.info.cycles
         r.rel = r.info.rel_residual
-        if r.id in self.keep:
+        if r.id in self.keep and r.status == TS_OK:
             with self.torch.cuda.stream(r.stream):
                 r.u_host = r.u.cpu().numpy()
+
+    @staticmethod
+    def _fail(r, now, code, msg):
+        """End one request with an error status; the others keep running."""
+        r.t_done = now
+        r.status = code
+        r.error = msg
 
     @staticmethod
     def _destroy_now(reqs):
@@ -203,15 +210,18 @@ class Server:
             # admission in arrival order, by slot and memory
             while waiting and n_active + len(setting_up) + len(to_setup) < self.max_active:
                 r = waiting[0]
+                if r.bytes > self.hbm_budget:
+                    # can never fit: rejected alone, the server goes on
+                    waiting.popleft()
+                    self._fail(r, now, TS_ENOMEM, "request needs %d bytes, over the HBM "
+                               "budget of %d" % (r.bytes, self.hbm_budget))
+                    continue
                 if used + r.bytes > self.hbm_budget:
                     if grave:
                         used -= sum(g.bytes for g in grave)
                         self._destroy(grave)
                         grave = []
                         continue
-                    if n_active + len(setting_up) + len(to_setup) == 0:
-                        raise RuntimeError("request %d needs %d bytes, over the HBM budget"
-                                           % (r.id, r.bytes))
                     break
                 waiting.popleft()
                 used += r.bytes
@@ -226,8 +236,15 @@ class Server:
             # requests whose set-up finished join the active set
             for fut in [f for f in setting_up if f.done()]:
                 r = setting_up.pop(fut)
-                fut.result()
+                err = fut.exception()
                 r.t_ready = time.perf_counter() - t0
+                if err is not None:
+                    # a failed set-up (device memory, non-finite data, ...)
+                    # ends this request only; its memory is released
+                    code = err.code if isinstance(err, TSError) else TS_EINVAL
+                    self._fail(r, r.t_ready, code, str(err))
+                    grave.append(r)
+                    continue
                 active[r.level].append(r)
                 n_active += 1
             progressed = False
@@ -260,7 +277,13 @@ class Server:
                 batch.append(r.sv)
                 inflight += w
             if batch:
-                ts_solve_batch_step(batch)
+                try:
+                    ts_solve_batch_step(batch)
+                except TSError:
+                    # the failing solver's solve has ended with the error as
+                    # its status (retired by the next query); solvers after
+                    # it were not stepped and stay ready
+                    pass
                 progressed = True
             if len(grave) >= self.gc_batch:
                 peak_dev = max(peak_dev, ts_device_bytes())
@@ -274,7 +297,8 @@ class Server:
         for fut in self.reaping:
             fut.result()
         self.reaping = []
-        torch.cuda.synchronize()
+        if any(r.t_admit is not None for r in reqs):
+            torch.cuda.synchronize()
         t_end = time.perf_counter() - t0
         summ = summarize(reqs, t_end, occ_area, peak_used, peak_dev)
         summ["levels_shared"] = self.shared
@@ -290,16 +314,17 @@ class Server:
 def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
     done = [r for r in reqs if r.t_done is not None]
     ok = [r for r in done if r.status == TS_OK]
-    lat = np.array([r.t_done - r.t for r in done]) if done else np.zeros(1)
+    # latency statistics over the requests that were served
+    lat = np.array([r.t_done - r.t for r in ok]) if ok else np.zeros(1)
     first = min(r.t for r in reqs)
     last = max(r.t_done for r in done) if done else first
     by_level = {}
-    for lvl in sorted({r.level for r in done}):
-        la = np.array([r.t_done - r.t for r in done if r.level == lvl])
+    for lvl in sorted({r.level for r in ok}):
+        la = np.array([r.t_done - r.t for r in ok if r.level == lvl])
         by_level[int(lvl)] = {"n": int(la.size),
                               "p50_ms": round(float(np.percentile(la, 50)) * 1e3, 2),
                               "p99_ms": round(float(np.percentile(la, 99)) * 1e3, 2),
-                              "cycles_mean": round(float(np.mean([r.cycles for r in done
+                              "cycles_mean": round(float(np.mean([r.cycles for r in ok
                                                                   if r.level == lvl])), 2)}
     return {
         "requests": len(reqs),
@@ -309,8 +334,12 @@ def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
         "solves_per_s": round(len(ok) / max(last - first, 1e-9), 3),
         "p50_latency_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
         "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-        "mean_setup_ms": round(float(np.mean([r.t_ready - r.t_admit for r in done])) * 1e3, 2),
-        "mean_queue_ms": round(float(np.mean([r.t_admit - r.t for r in done])) * 1e3, 2),
+        "failed_by_status": {str(c): sum(1 for r in done if r.status == c)
+                             for c in sorted({r.status for r in done if r.status != TS_OK})},
+        "mean_setup_ms": round(float(np.mean([r.t_ready - r.t_admit for r in ok])) * 1e3, 2)
+        if ok else None,
+        "mean_queue_ms": round(float(np.mean([r.t_admit - r.t for r in ok])) * 1e3, 2)
+        if ok else None,
         "mean_active": round(occ_area / max(t_end, 1e-9), 2),
         "peak_admitted_gb": round(peak_used / 2 ** 30, 3),
         "peak_library_gb": round(peak_dev / 2 ** 30, 3),

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -60,3 +61,26 @@ def test_batched_step_rejects_bad_batches_without_gpu():
     arr1 = (ctypes.c_void_p * 1)(None)
     assert L.ts_solve_batch_step(arr1, 1) == ts.TS_EINVAL
     assert "null solver" in ts.ts_last_error()
+
+
+def test_vector_checks_reject_before_the_library():
+    # the binding refuses vectors the kernels would overrun (wrong element
+    # type, strided, short or long, host memory) with TS_EINVAL before any
+    # library call; the device check comes last so that the others can be
+    # exercised with host tensors
+    import torch
+
+    import paper_1608_06473_amd as ts
+    n = 100
+    cases = [(torch.zeros(n, dtype=torch.float32), ts.TS_F64, "dtype"),
+             (torch.zeros(n, dtype=torch.float64), ts.TS_F32, "dtype"),
+             (torch.zeros(2 * n, dtype=torch.float64)[::2], ts.TS_F64, "contiguous"),
+             (torch.zeros(n - 1, dtype=torch.float64), ts.TS_F64, "entries"),
+             (torch.zeros(n + 1, dtype=torch.float32), ts.TS_F16W, "entries"),
+             (torch.zeros(n, dtype=torch.float64), ts.TS_F64, "device"),
+             (np.zeros(n), ts.TS_F64, "dtype")]
+    for t, dt, what in cases:
+        with pytest.raises(ts.TSError) as e:
+            ts.check_vector(t, n, dt, "x")
+        assert e.value.code == ts.TS_EINVAL
+        assert what in str(e.value), (what, str(e.value))

@@ -42,3 +42,23 @@ def test_admission_estimate_covers_the_vectors():
     # a level-7 request of the 288-macro shell is a few GB, far below one
     # GPU's 288 GB
     assert 2e9 < request_bytes(288, 7, TS_F32) < 2e10
+
+
+def test_request_over_the_budget_is_rejected_alone():
+    # a request that can never fit the HBM budget retires with TS_ENOMEM at
+    # admission; the loop goes on and ends normally (no set-up is started, so
+    # this runs without a GPU)
+    from paper_1608_06473_amd import TS_ENOMEM
+    from paper_1608_06473_amd.serve import Server, request_bytes
+    trace = [{"id": 0, "t": 0.0, "level": 7, "r_in": 0.55},
+             {"id": 1, "t": 0.001, "level": 6, "r_in": 0.5}]
+    srv = Server(hbm_budget=request_bytes(288, 4), max_active=4)
+    try:
+        reqs, summ = srv.run(trace)
+    finally:
+        srv.close()
+    assert [r.status for r in reqs] == [TS_ENOMEM, TS_ENOMEM]
+    assert all(r.t_admit is None and r.t_done is not None for r in reqs)
+    assert "HBM budget" in reqs[0].error
+    assert summ["failed"] == 2 and summ["completed_ok"] == 0
+    assert summ["failed_by_status"] == {str(TS_ENOMEM): 2}

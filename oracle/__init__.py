@@ -28,17 +28,30 @@ DIRS = np.array(
 NAMES = ["mc", "mw", "me", "ms", "mn", "mse", "mnw", "bc", "be", "bn", "bnw", "tc", "tw",
          "ts", "tse"]
 
-IFEM, LSQP, IPOLY, SYM = 0, 1, 2, 3
+IFEM, LSQP, IPOLY, SYM, CONS = 0, 1, 2, 3, 4
 
 
 def _opkind(kind):
     """operator kind of the C oracle: 0 element-wise, 1 surrogate (15
-    polynomials per macro), 2 symmetric surrogate (7 edge polynomials)"""
-    return 0 if kind == IFEM else 2 if kind == SYM else 1
+    polynomials per macro), 2 symmetric surrogate (7 edge polynomials), 3
+    constant stencils of the unmapped macros on the volume"""
+    return {IFEM: 0, SYM: 2, CONS: 3}.get(kind, 1)
 
 
 def build(force=False):
-    """Compile the oracle with gcc (plain C, OpenMP over rows)."""
+    """Compile the oracle with gcc (plain C, OpenMP over rows).
+
+    With TS_ORACLE_NATIVE=1 in the environment (the benchmark's CPU leg) a
+    second copy is built for the host it runs on (-O3 -march=native) in the
+    temporary directory and used instead; the tests use the portable -O2
+    build."""
+    if os.environ.get("TS_ORACLE_NATIVE") == "1":
+        import tempfile
+        lib_path = os.path.join(tempfile.gettempdir(), "libtsoracle_native_%d.so" % os.getpid())
+        cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-o", lib_path,
+               _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        return lib_path
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
@@ -53,8 +66,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(build())
         P, I64, I, D = C.c_void_p, C.c_int64, C.c_int, C.c_double
         sig = {
             "or_mesh_new": (P, [P, I64, P, I64, I]),
@@ -116,6 +128,8 @@ def lib():
             "or_fit_sym_values": (I, [I, I, I, P, P]),
             "or_poly_eval_mid": (D, [I, I, P, I, I, I, I]),
             "or_solve_dd": (I, [P, P, P, D, I, P]),
+            "or_gs_rows": (None, [P, I, I, I, I, P, P, P, P, I64, P]),
+            "or_row_neighbours": (I, [P, I, I64, P, I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -267,6 +281,23 @@ class Mesh:
         cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
         lib().or_gs_sweep(self.h, N, _opkind(kind), q, center, _p(cf), _p(f), _p(u))
         return u
+
+    def gs_rows(self, N, f, x, rows, kind=IFEM, q=2, center=0, coeffs=None):
+        """Gauss-Seidel values (f_u - off_u(x)) / diag_u of the listed rows."""
+        _set_flags(None)
+        f, x = _f64(f), _f64(x)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.zeros(rows.shape[0])
+        cf = _f64(coeffs) if coeffs is not None else np.zeros(1)
+        lib().or_gs_rows(self.h, N, _opkind(kind), q, center, _p(cf), _p(f), _p(x), _p(rows),
+                         rows.shape[0], _p(out))
+        return out
+
+    def row_neighbours(self, N, u):
+        """Free unique nodes sharing a fine edge with node u."""
+        out = np.zeros(256, dtype=np.int64)
+        n = lib().or_row_neighbours(self.h, N, int(u), _p(out), 256)
+        return out[:n]
 
     def prolongate(self, N, uc):
         uc = _f64(uc)

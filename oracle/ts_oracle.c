@@ -414,8 +414,18 @@ int or_copies(const or_mesh *M, int N, int64_t u, int64_t *ct, int *cijk, int ma
 /* geometry: Psi_T then Phi_T                                                */
 /* ------------------------------------------------------------------------ */
 
+static void node_xyz_g(const or_mesh *M, int N, int64_t t, int i, int j, int k,
+                       double x[3], int affine);
 static void node_xyz(const or_mesh *M, int N, int64_t t, int i, int j, int k,
                      double x[3]) {
+    node_xyz_g(M, N, t, i, j, k, x, M->affine);
+}
+
+/* The fine node (i, j, k) of macro t: the affine point y = Psi_T((i,j,k)/N)
+   (affine != 0: Phi = Id, the unmapped macro) or its blended image
+   x = rho(y) y / |y| (Sec. 2.2). */
+static void node_xyz_g(const or_mesh *M, int N, int64_t t, int i, int j, int k,
+                       double x[3], int affine) {
     const int64_t *g = M->tet + 4 * t;
     int mu[4] = {N - i - j - k, i, j, k};
     /* sum over the macro vertices in ascending global-id order, so that every
@@ -431,7 +441,7 @@ static void node_xyz(const or_mesh *M, int N, int64_t t, int i, int j, int k,
         for (int d = 0; d < 3; d++) y[d] += w * M->vtx[3 * g[a] + d];
         rho += w * M->vrad[g[a]];
     }
-    if (M->affine) {
+    if (affine) {
         for (int d = 0; d < 3; d++) x[d] = y[d];
         return;
     }
@@ -1055,8 +1065,12 @@ int or_face_row_exact(const or_mesh *M, int N, int64_t u, double *s, int64_t *nb
 /* Operator on one level: kind 0 = IFEM everywhere; kind 1 = surrogate rows on
    the volume primitives (coefficients nt x 15 x m_q) with IFEM rows on the
    lower primitives (Sec. 3.4); kind 2 = the symmetric surrogate (coefficients
-   nt x 7 x m_q, one per edge direction, centre from the row sum).  center 0:
-   own polynomial for mc; 1: mc from the row sum (Alg. 1). */
+   nt x 7 x m_q, one per edge direction, centre from the row sum); kind 3 =
+   the constant stencil of the unmapped geometry on the volume primitives
+   (the paper's lower bound in Sec. 4.2.1 and Sec. 5: the volume rows of the
+   fine tetrahedra of the affine macro, Phi = Id, with IFEM rows of the mesh
+   geometry on the lower primitives).  center 0: own polynomial for mc; 1: mc
+   from the row sum (Alg. 1). */
 typedef struct {
     int kind, q, center;
     const double *coeffs;
@@ -1083,8 +1097,15 @@ int or_gs_phase(const or_mesh *M, int N, int64_t u) {
 /* IFEM row (Sec. 2.3): sum over every copy of the node and every fine
    tetrahedron at that copy of the stiffness row; diag = a_II and
    off = sum_{J != I} a_IJ x_J with x = 0 at Dirichlet nodes. */
+static void row_ifem_g(const or_mesh *M, int N, const int64_t *ct, int (*cijk)[3], int nc,
+                       const double *x, double *diag, double *off, int affine);
 static void row_ifem(const or_mesh *M, int N, const int64_t *ct, int (*cijk)[3], int nc,
                      const double *x, double *diag, double *off) {
+    row_ifem_g(M, N, ct, cijk, nc, x, diag, off, M->affine);
+}
+/* affine != 0: the fine tetrahedra of the unmapped macros (Phi = Id) */
+static void row_ifem_g(const or_mesh *M, int N, const int64_t *ct, int (*cijk)[3], int nc,
+                       const double *x, double *diag, double *off, int affine) {
     double dg = 0, of = 0;
     for (int c = 0; c < nc; c++) {
         int tl[32][4][3];
@@ -1092,7 +1113,7 @@ static void row_ifem(const or_mesh *M, int N, const int64_t *ct, int (*cijk)[3],
         for (int q = 0; q < nt; q++) {
             double xx[4][3], K[4];
             for (int v = 0; v < 4; v++)
-                node_xyz(M, N, ct[c], tl[q][v][0], tl[q][v][1], tl[q][v][2], xx[v]);
+                node_xyz_g(M, N, ct[c], tl[q][v][0], tl[q][v][1], tl[q][v][2], xx[v], affine);
             stiff_row0(xx, K, NULL);
             dg += K[0];
             for (int v = 1; v < 4; v++) {
@@ -1177,6 +1198,10 @@ static void row_volume(const or_mesh *M, int N, const or_op *op, int64_t t, int 
         row_surrogate_sym(M, N, op, t, i, j, k, x, diag, off);
     } else if (op->kind == 1 && !(op->ifem && op->ifem[t])) {
         row_surrogate(M, N, op, t, i, j, k, x, diag, off);
+    } else if (op->kind == 3) {
+        int64_t ct[1] = {t};
+        int cijk[1][3] = {{i, j, k}};
+        row_ifem_g(M, N, ct, cijk, 1, x, diag, off, 1);
     } else {
         int64_t ct[1] = {t};
         int cijk[1][3] = {{i, j, k}};
@@ -1288,6 +1313,45 @@ void or_apply_rows(const or_mesh *M, int N, int kind, int q, int center,
         row_eval(M, N, &op, u, x, &dg, &of);
         y[r] = dg * x[u] + of;
     }
+}
+
+/* The Gauss-Seidel update of eq. iteration-scheme at the listed rows,
+   out[r] = (f_u - sum_{J != u} a_uJ x_J) / a_uu with the row of unique node
+   u = rows[r] (as in or_gs_sweep); 0 on Dirichlet rows.  With x the values
+   at the start of a node's phase this is the value the sweep gives it. */
+void or_gs_rows(const or_mesh *M, int N, int kind, int q, int center, const double *coeffs,
+                const double *f, const double *x, const int64_t *rows, int64_t nrows,
+                double *out) {
+    or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < nrows; r++) {
+        int64_t u = rows[r];
+        if (or_is_dirichlet(M, N, u)) { out[r] = 0; continue; }
+        double dg, of;
+        row_eval(M, N, &op, u, x, &dg, &of);
+        out[r] = (f[u] - of) / dg;
+    }
+}
+
+/* Unique ids of the free nodes that share a fine edge with node u: the
+   neighbours in the 14 stencil directions of every copy of u that stay in
+   that copy's macro, each once.  Returns their number (at most maxn). */
+int or_row_neighbours(const or_mesh *M, int N, int64_t u, int64_t *out, int maxn) {
+    int64_t ct[256];
+    int cijk[256][3];
+    int nc = copies(M, N, u, ct, cijk, 256), n = 0;
+    for (int c = 0; c < nc; c++)
+        for (int w = 1; w < NW; w++) {
+            int i = cijk[c][0] + DIR[w][0], j = cijk[c][1] + DIR[w][1], k = cijk[c][2] + DIR[w][2];
+            if (i < 0 || j < 0 || k < 0 || i + j + k > N) continue;
+            int dir;
+            int64_t v = canon_d(M, N, ct[c], i, j, k, &dir);
+            if (dir) continue;
+            int seen = 0;
+            for (int e = 0; e < n; e++) seen |= out[e] == v;
+            if (!seen && n < maxn) out[n++] = v;
+        }
+    return n;
 }
 
 /* r = f - L u on the free rows, 0 on Dirichlet rows. */

@@ -923,3 +923,65 @@ def test_sym_surrogate_accuracy_matches_lsqp(orc):
     es = np.abs(M.apply(N, x, kind=orc.SYM, q=2, coeffs=M.fit_sym(N, 2, 2)) - yi).max()
     el = np.abs(M.apply(N, x, kind=orc.LSQP, q=2, coeffs=M.fit(N, orc.LSQP, 2, 2)) - yi).max()
     assert 0 < es < 1.5 * el
+
+
+# --------------------------------------------------------------------------
+# constant stencil of the unmapped geometry (Sec. 4.2.1 Tab. flops, the
+# 29-FLOP kernel; Sec. 5 introduction: the cycle time on unprojected macros)
+# --------------------------------------------------------------------------
+
+def _volume_rows(orc, M, N):
+    n_lower = M.nv + M.ne * (N - 1) + M.nf * (N - 1) * (N - 2) // 2
+    return np.arange(n_lower, M.num_unique(N)), n_lower
+
+
+def test_cons_on_affine_mesh_is_ifem(orc):
+    # with Phi = Id the constant stencil is the exact operator (Sec. 2.3: the
+    # stencils of an affine macro do not vary)
+    v, t = inputs.shell288()
+    M = orc.Mesh(v, t, affine=True)
+    N = 8
+    x = inputs.uniform(M.num_unique(N), 3)
+    yc = M.apply(N, x, kind=orc.CONS)
+    yi = M.apply(N, x, kind=orc.IFEM)
+    assert np.array_equal(yc, yi)
+
+
+def test_cons_volume_rows_are_the_unmapped_stencils(orc):
+    # on the shell the constant stencil takes the volume rows of the affine
+    # macros and the lower-primitive rows of the blended geometry: it equals
+    # the affine mesh's IFEM operator on volume rows, the shell's elsewhere
+    v, t = inputs.shell288()
+    S, A = orc.Mesh(v, t), orc.Mesh(v, t, affine=True)
+    N = 8
+    x = inputs.uniform(S.num_unique(N), 4)
+    x[S.dirichlet_mask(N)] = 0
+    yc = S.apply(N, x, kind=orc.CONS)
+    vol, nl = _volume_rows(orc, S, N)
+    assert np.array_equal(yc[vol], A.apply(N, x, kind=orc.IFEM)[vol])
+    assert np.array_equal(yc[:nl], S.apply(N, x, kind=orc.IFEM)[:nl])
+    # and it is not the blended operator there (the test discriminates)
+    yi = S.apply(N, x, kind=orc.IFEM)
+    assert np.abs(yc[vol] - yi[vol]).max() > 1e-3 * np.abs(yi[vol]).max()
+
+
+def test_cons_annihilates_affine_linears_on_the_shell(orc):
+    # P1 on a straight tetrahedral mesh is exact for linear functions: a row
+    # whose 15 neighbours lie in one unmapped macro gives 0 for u linear in
+    # the affine (unprojected) coordinates, for any shell geometry
+    v, t = inputs.shell288()
+    S, A = orc.Mesh(v, t), orc.Mesh(v, t, affine=True)
+    N = 16
+    y = A.coords(N)
+    x = 0.3 + y @ np.array([1.0, -2.0, 0.5])
+    r = S.apply(N, x, kind=orc.CONS)
+    ids = S.block_canon_ids(N)
+    from oracle.brute import local_nodes
+    loc = local_nodes(N)
+    deep = [n for n, p in enumerate(loc) if min(p) >= 2 and p.sum() <= N - 2]
+    B = orc.block_size(N)
+    rows = np.concatenate([ids[m * B + np.array(deep)] for m in range(S.nt)])
+    scale = np.abs(S.apply(N, x, kind=orc.IFEM)[rows]).max()
+    assert np.abs(r[rows]).max() < 1e-12 * max(scale, 1.0)
+    # the blended operator does not annihilate them
+    assert scale > 1e-6

@@ -64,20 +64,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic():
-    """HBM bytes per launch of the volume kernel from the committed counter
-    summary (its `record:` line: FETCH_SIZE and WRITE_SIZE in KiB per
-    dispatch, scaled by the factors measured on a plain device copy), or None
-    when the summary is missing or was taken on another version of the kernel
-    source."""
+def pmc_traffic(key="record"):
+    """HBM bytes per launch from the committed counter summary (its `record:`
+    line for the volume-only launch, `record_whole:` for the whole-operator
+    launch: FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the
+    factors measured on a plain device copy), or None when the summary is
+    missing or was taken on another version of the kernel source."""
     path = os.path.join(ROOT, PMC_RECORD)
     if not os.path.exists(path):
         return None
     rec = None
+    tag = key + ": "
     with open(path) as fh:
         for ln in fh:
-            if ln.startswith("record: "):
-                rec = json.loads(ln[len("record: "):])
+            if ln.startswith(tag):
+                rec = json.loads(ln[len(tag):])
     if rec is None:
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
@@ -295,6 +296,11 @@ def main():
     ms = dt / args.steps * 1e3
     value = info.n_free * args.steps / dt / 1e9
     log("full apply: %.3f ms/step, %.1f GDoF/s" % (ms, value))
+    # the whole-operator launch (volume rows with the face rows fused in, edge
+    # and vertex rows beside it on the operator's side stream), HIP events on
+    # the caller's stream, which joins the side stream
+    whole_ms = time_events(step, max(5, args.steps), stream)
+    whole_alg = 16.0 * info.n_free
 
     # dominant kernel: the surrogate volume kernel, HIP events on its stream
     reps = max(5, args.steps)
@@ -335,6 +341,26 @@ def main():
                          "volume_gbs": round(alg_bytes / (q4_vol / 1e3) / 1e9, 1)}
     log("q=4 apply: %.3f ms (volume %.3f ms)" % (q4_ms, q4_vol))
     del op4
+    # the constant stencil of the unmapped macros (the paper's 29-FLOP lower
+    # bound): apply, volume kernel, residual and a Gauss-Seidel sweep
+    opC = ts.Operator(G, lam, method=ts.TS_CONS)
+    ts.ts_apply(opC.h, lam, ts.TS_F64, xb, yb, stream)
+    c_ms = time_events(lambda: ts.ts_apply(opC.h, lam, ts.TS_F64, xb, yb, stream), reps, stream)
+    c_vol = time_events(lambda: ts.ts_apply_volume(opC.h, lam, ts.TS_F64, xb, yb, stream), reps,
+                        stream)
+    rC = G.zeros(lam)
+    c_res = time_events(lambda: ts.ts_residual(opC.h, lam, ts.TS_F64, xb, xb, rC, stream), reps,
+                        stream)
+    uC = xb.clone()
+    c_gs = time_events(lambda: ts.ts_smooth(opC.h, lam, ts.TS_F64, xb, uC, 1, stream), 3, stream)
+    extra["cons_apply"] = {"ms": round(c_ms, 4), "gdofs": round(info.n_free / c_ms / 1e6, 3),
+                           "volume_ms": round(c_vol, 4),
+                           "volume_gbs": round(alg_bytes / (c_vol / 1e3) / 1e9, 1),
+                           "residual_ms": round(c_res, 4), "gs_sweep_ms": round(c_gs, 4),
+                           "surrogate_q2_over_cons": round(ms / c_ms, 3)}
+    log("constant-stencil apply: %.3f ms (volume %.3f ms), residual %.3f ms, GS sweep %.3f ms"
+        % (c_ms, c_vol, c_res, c_gs))
+    del opC, rC, uC
     # the symmetric surrogate (edge polynomials at the midpoints, centre from
     # the row sum): the same volume kernel in its row-sum mode
     opS = ts.Operator(G, lam, method=ts.TS_LSQP_SYM, q=q, sample_j=2)
@@ -426,6 +452,14 @@ def main():
                      "kernel_ms": round(vol_ms, 4),
                      "algorithmic_bytes": int(alg_bytes),
                      "kernel_source_hash": kernel_source_hash()},
+        "roofline_whole_operator": {
+            "bound": "hbm", "achieved": round(whole_alg / (whole_ms / 1e3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(whole_alg / (whole_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": pmc_traffic("record_whole"),
+            "launch": "ts_apply: k_surr_lds with the face rows fused in, edge and vertex rows "
+                      "on the side stream, Dirichlet rows zeroed",
+            "ms": round(whole_ms, 4), "algorithmic_bytes": int(whole_alg)},
         "cpu_baseline": cpu,
     }
     line.update(extra)

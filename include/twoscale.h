@@ -61,12 +61,20 @@ enum {
 };
 
 enum { TS_GEOM_SHELL = 0, TS_GEOM_AFFINE = 1 };
-/* TS_LSQP_SYM: the symmetric surrogate of the remark at the end of Sec. 3.3,
+/* TS_LSQP_SYM: the symmetric surrogate of the remark at the end of Sec. 3.4,
  * one polynomial per edge direction evaluated at the edge midpoint, fitted by
  * least squares like LSQP to the exact weights of both directions; the centre
  * weight is minus the sum of the others (the operator's centre mode is set to
  * TS_CENTER_ROWSUM), so the volume rows of a macro form a symmetric matrix. */
-enum { TS_IFEM = 0, TS_LSQP = 1, TS_IPOLY = 2, TS_LSQP_SYM = 3 };
+/* TS_CONS: the constant-stencil operator the paper takes as the lower bound
+ * of the method's cost (Sec. 4.2.1 Tab. flops: 29 FLOP per update; Sec. 5
+ * introduction: the cycle time on unprojected geometry).  Each macro's volume
+ * rows use one stencil, the exact stencil of the macro's unmapped fine
+ * tetrahedra (Phi = Id there); the lower-primitive rows are those of the
+ * mesh geometry, as for every method.  On a TS_GEOM_AFFINE mesh it is the
+ * exact operator.  q, sample_j are ignored; no face surrogate, no fallback
+ * check. */
+enum { TS_IFEM = 0, TS_LSQP = 1, TS_IPOLY = 2, TS_LSQP_SYM = 3, TS_CONS = 4 };
 enum { TS_CENTER_POLY = 0, TS_CENTER_ROWSUM = 1 };
 enum { TS_F64 = 0, TS_F32 = 1, TS_F16W = 2 };
 enum { TS_RHS_MANUFACTURED = 0, TS_RHS_BUMPS = 1, TS_RHS_ONE = 2 };
@@ -83,8 +91,8 @@ typedef struct {
 } ts_layout_info;
 
 typedef struct {
-    int method;   /* TS_LSQP, TS_IPOLY, TS_LSQP_SYM or TS_IFEM (exact on-the-fly
-                     assembly) */
+    int method;   /* TS_LSQP, TS_IPOLY, TS_LSQP_SYM, TS_CONS or TS_IFEM (exact
+                     on-the-fly assembly) */
     int q;        /* surrogate degree 1..4 (IPOLY: 2) */
     int sample_j; /* LSQP sampling set M_{m(l,j)}, m = min(l, max(1, j)) */
     int center;   /* TS_CENTER_POLY or TS_CENTER_ROWSUM */
@@ -118,7 +126,7 @@ typedef struct {
     double rtol;         /* stop when ||f - L u||_2 <= rtol ||f||_2 (free rows) */
     int diverge_window;  /* stop with TS_ENOCONV after this many consecutive
                             residual increases (0: default 3) */
-    int dd;              /* non-zero: double discretisation (Sec. 4.1).  The
+    int dd;              /* non-zero: double discretisation (Sec. 4 introduction).  The
                             smoothing sweeps use the operator's surrogate
                             stencils, every residual of the cycle the exact
                             element-wise (IFEM) rows; the two operators

@@ -130,6 +130,7 @@ def lib():
             "or_solve_dd": (I, [P, P, P, D, I, P]),
             "or_gs_rows": (None, [P, I, I, I, I, P, P, P, P, I64, P]),
             "or_row_neighbours": (I, [P, I, I64, P, I]),
+            "or_set_gs_order": (None, [I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -400,7 +401,7 @@ class Multigrid:
 
     def solve_dd(self, f, u0=None, rtol=1e-10, max_cycles=50):
         """Cycles until the relative update ||u_c - u_(c-1)|| / ||u_c|| <= rtol
-        (the stop test of double discretisation, Sec. 4.1)."""
+        (the stop test of double discretisation, Sec. 4 introduction)."""
         f = _f64(f)
         u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
         hist = np.zeros(max_cycles)
@@ -429,6 +430,13 @@ def _set_flags(flags, fcoeffs=None):
         a = _f64(fcoeffs)
         _flag_keep[1] = a
         lib().or_set_face_coeffs(_p(a))
+
+
+def set_gs_order(mode):
+    """Ordering of every following Gauss-Seidel sweep of the oracle: 0 the
+    multicolour phases (default), 1 the interface nodes one after the other
+    in canonical order, 2 every node one after the other (lexicographic)."""
+    lib().or_set_gs_order(int(mode))
 
 
 def num_coeffs2(q):

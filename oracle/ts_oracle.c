@@ -740,7 +740,7 @@ int or_fit(const or_mesh *M, int N, int method, int q, int jsamp, double *coeffs
 }
 
 /* ------------------------------------------------------------------------ */
-/* symmetric surrogate (remark at the end of Sec. 3.3): one polynomial per   */
+/* symmetric surrogate (remark at the end of Sec. 3.4): one polynomial per   */
 /* edge direction, evaluated at the midpoint of the edge                     */
 /* ------------------------------------------------------------------------ */
 
@@ -1366,14 +1366,41 @@ void or_residual(const or_mesh *M, int N, int kind, int q, int center,
 /* One multicolour Gauss-Seidel sweep (eq. iteration-scheme): phases 0..9 in
    order; inside a phase every node is updated from the values at the start
    of that phase. */
+/* Ordering of the sweep (an experiment on the smoother, not the operator):
+   0 the multicolour phases below (default); 1 the same volume colours, but
+   every free face, edge and vertex node updated one after the other in
+   canonical order, each from the newest values (true Gauss-Seidel on the
+   interface); 2 every free node one after the other in canonical order
+   (interface, then each macro's interior with i fastest: the lexicographic
+   Gauss-Seidel of eq. iteration-scheme). */
+static int g_gs_order = 0;
+void or_set_gs_order(int mode) { g_gs_order = mode; }
+
+static void gs_node_seq(const or_mesh *M, int N, const or_op *op, const double *f, double *u,
+                        int64_t v) {
+    if (or_is_dirichlet(M, N, v)) return;
+    double dg, of;
+    row_eval(M, N, op, v, u, &dg, &of);
+    u[v] = (f[v] - of) / dg;
+}
+
 void or_gs_sweep(const or_mesh *M, int N, int kind, int q, int center,
                  const double *coeffs, const double *f, double *u) {
     or_op op = {kind, q, center, coeffs, g_flags, g_fcoef};
     int64_t nu = or_num_unique(M, N);
     int64_t vb = vol_base(M, N);
     int64_t V = n_vol_int(N);
+    if (g_gs_order == 2) {
+        for (int64_t v = 0; v < nu; v++) gs_node_seq(M, N, &op, f, u, v);
+        return;
+    }
     double *nw = malloc(sizeof(double) * nu);
     for (int p = 0; p < 10; p++) {
+        if (g_gs_order == 1 && p < 6) {
+            if (p == 0)
+                for (int64_t v = 0; v < vb; v++) gs_node_seq(M, N, &op, f, u, v);
+            continue;
+        }
         rows_ctx c = {u, f, nw};
         for_rows(M, N, &op, u, p, cb_gs, &c);
         if (p < 6) {
@@ -1550,7 +1577,7 @@ void or_coarse_solve(const or_coarse *C, const or_mesh *M, const double *f, doub
 /* levels: N = 2^lam for lam = lam0 .. lamL; lam0 uses IFEM and the coarse
    solve; every finer level uses the operator (kind, q, center) with its own
    coefficients coeffs[lam - lam0] (NULL entries are allowed for IFEM).
-   dd != 0 selects double discretisation (Sec. 4.1): the smoothing sweeps keep
+   dd != 0 selects double discretisation (Sec. 4 introduction): the smoothing sweeps keep
    the operator (kind, q, center) while every residual r = f - L u uses the
    exact IFEM operator L. */
 typedef struct {
@@ -1669,7 +1696,7 @@ int or_solve(const or_mg *G, const double *f, double *u, double rtol,
     return rel <= rtol ? c : -1;
 }
 
-/* Double-discretisation solve (Sec. 4.1): with two operators in the cycle the
+/* Double-discretisation solve (Sec. 4 introduction): with two operators in the cycle the
    residual does not go to zero, so the stop test is on the update instead,
    ||u_c - u_{c-1}||_2 <= rtol ||u_c||_2 over the free rows.  Returns the
    number of cycles (or -1 when max_cycles is reached); hist[c - 1] gets the

@@ -10,7 +10,7 @@ Method: Bauer et al., "A two-scale approach for efficient on-the-fly operator
 assembly in massively parallel high performance multigrid codes" (arXiv
 1608.06473): P1 finite elements on refined macro tetrahedra of a spherical
 shell, volume stencils from surrogate polynomials (Sec. 3), multigrid
-(Sec. 4.1).
+(Sec. 4 introduction).
 """
 from __future__ import annotations
 
@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libtwoscale.so")
 
 TS_OK, TS_EINVAL, TS_ENOMEM, TS_EHIP, TS_ENOCONV, TS_ENONFINITE = range(6)
 TS_GEOM_SHELL, TS_GEOM_AFFINE = 0, 1
-TS_IFEM, TS_LSQP, TS_IPOLY, TS_LSQP_SYM = 0, 1, 2, 3
+TS_IFEM, TS_LSQP, TS_IPOLY, TS_LSQP_SYM, TS_CONS = 0, 1, 2, 3, 4
 TS_CENTER_POLY, TS_CENTER_ROWSUM = 0, 1
 TS_F64, TS_F32, TS_F16W = 0, 1, 2
 TS_RHS_MANUFACTURED, TS_RHS_BUMPS, TS_RHS_ONE = 0, 1, 2
@@ -415,6 +415,8 @@ class Operator:
     def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
                  fallback_tol=0.0, stream=None, face_surrogate=False):
         self.mesh = mesh
+        if method == TS_CONS:
+            q = 0  # one constant stencil per macro: degree-0 coefficients
         self.method, self.q = method, q
         self.max_level = max_level
         self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol,

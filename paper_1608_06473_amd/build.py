@@ -15,8 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtwoscale.so")
 SOURCES = ["ts_topology.cpp", "ts_api.cpp", "k_stencil.hip", "k_misc.hip"]
-# the surrogate volume kernel, one unit per (degree q, staging width kpt)
-INST = [(q, k) for q in (1, 2, 3, 4) for k in (2, 4, 8)]
+# the surrogate volume kernel, one unit per (degree q, staging width kpt);
+# q = 0 is the constant stencil
+INST = [(q, k) for q in (0, 1, 2, 3, 4) for k in (2, 4, 8)]
 # the IFEM volume kernel, one unit per staging width (levels up to 8)
 IFEM_KPT = (2, 4)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -620,6 +620,28 @@ __global__ __launch_bounds__(128) void k_sample(double* __restrict__ Bout, const
 
 __device__ __forceinline__ int basis_row(int q, int N, int i, int j, int k, double* row);
 
+// Constant stencils (the volume rows of the unmapped macro, Phi = Id; the
+// paper's constant-stencil lower bound, Tab. flops): the exact stencil of the
+// affine macro's fine tetrahedra at its interior node (1, 1, 1), which is the
+// stencil of every interior node.  One thread per macro: coef[m][15].
+__global__ __launch_bounds__(64) void k_cons_stencils(double* __restrict__ coef,
+                                                      const MacroGeom* __restrict__ geom, int nt,
+                                                      int N) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nt) return;
+    MacroGeom g = geom[m];
+    g.affine = 1;
+    double st[NW];
+    ifem_partial_stencil(g, N, 1, 1, 1, st);
+    for (int w = 0; w < NW; w++) coef[(size_t)m * NW + w] = st[w];
+}
+
+void launch_cons_stencils(const Mesh& M, int lam, double* coef, hipStream_t s) {
+    const int nt = (int)M.nt;
+    k_cons_stencils<<<(nt + 63) / 64, 64, 0, s>>>(coef, M.d_geom.p, nt, 1 << lam);
+    TS_HIP(hipGetLastError());
+}
+
 // Selective surrogate check (remark in Sec. 3.4): one thread per macro
 // compares the exact centre weight with the surrogate's centre polynomial at
 // five interior points near the macro's vertices and centre.
@@ -765,7 +787,7 @@ void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt,
     TS_HIP(hipGetLastError());
 }
 
-// Symmetric surrogate (the remark at the end of Sec. 3.3): one polynomial
+// Symmetric surrogate (the remark at the end of Sec. 3.4): one polynomial
 // per edge direction pair (w, wo), fitted to the exact weights of both
 // directions at the edge midpoints.  A midpoint i + w/2 is an integer point
 // of the level with 2N intervals, so the pair's points are given in doubled

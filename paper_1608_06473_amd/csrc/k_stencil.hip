@@ -353,6 +353,7 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
                                  int center, int mode, const void* x, void* y,            \
                                  const void* f, int colour, hipStream_t s,                \
                                  const double* f2sten, const double* f2coef);
+TS_DECL(0, 2) TS_DECL(0, 4) TS_DECL(0, 8)
 TS_DECL(1, 2) TS_DECL(1, 4) TS_DECL(1, 8)
 TS_DECL(2, 2) TS_DECL(2, 4) TS_DECL(2, 8)
 TS_DECL(3, 2) TS_DECL(3, 4) TS_DECL(3, 8)
@@ -376,6 +377,9 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     const double* fc = f2 && lo.face_fit ? lo.fcoef.p : nullptr;
 #define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s, f2, fc)
     switch (q * 16 + kpt) {
+        case 2: TS_GO(0, 2); break;
+        case 4: TS_GO(0, 4); break;
+        case 8: TS_GO(0, 8); break;
         case 18: TS_GO(1, 2); break;
         case 20: TS_GO(1, 4); break;
         case 24: TS_GO(1, 8); break;

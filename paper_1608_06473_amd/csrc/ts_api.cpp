@@ -1,6 +1,6 @@
 // C ABI of the two-scale library: host orchestration of the kernels.
 // Setup of the surrogate (Sec. 3.1-3.3), operator application and smoothing
-// (Sec. 3.4, eq. iteration-scheme), V(nu1, nu2) multigrid (Sec. 4.1) with an
+// (Sec. 3.4, eq. iteration-scheme), V(nu1, nu2) multigrid (Sec. 4 introduction) with an
 // exact FP64 coarsest level, and the FP64 / mixed-precision solve.
 #include <math.h>
 #include <string.h>
@@ -120,7 +120,18 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
     auto lo = std::make_unique<LevelOp>();
     lo->lam = lam;
     M.level(lam);
-    if (op->p.method != TS_IFEM && lam >= 3) {
+    if (op->p.method == TS_CONS && lam >= 3) {
+        // one stencil per macro: the exact stencil of its unmapped fine
+        // tetrahedra, the same at every interior node (degree-0 coefficients)
+        lo->coef64.alloc((size_t)M.nt * NW);
+        launch_cons_stencils(M, lam, lo->coef64.p, s);
+        std::vector<double> h((size_t)M.nt * NW);
+        TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        TS_HIP(hipStreamSynchronize(s));
+        for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite constant stencil");
+        upload_coef_variants(op, *lo, lam, h);
+        split_macros(op, *lo, lam, s);
+    } else if (op->p.method != TS_IFEM && lam >= 3) {
         const int N = 1 << lam, q = op->p.q, mq = op->mq;
         std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
         const int np = (int)pts.size() / 3;
@@ -159,6 +170,10 @@ static double* iface_tmp(const ts_op* op, int lam) {
 
 // levels from which the lower-primitive rows run on the side stream
 constexpr int kForkLevel = 6;
+// face rows inside the surrogate volume launch (1) or as their own launch (0)
+#ifndef TS_FUSE_FACE
+#define TS_FUSE_FACE 1
+#endif
 
 // y = L x (mode 0) or y = f - L x (mode 1).  The lower-primitive rows and the
 // volume rows write disjoint slots, so on large levels the former run on the
@@ -168,7 +183,7 @@ static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x
                     const void* f, hipStream_t s, bool exact = false) {
     const bool sur = !exact && uses_surrogate(op, lam);
     // the face rows run inside the surrogate volume launch when it has work
-    const bool fuse = sur && op->lv.at(lam)->n_sur > 0;
+    const bool fuse = TS_FUSE_FACE && sur && op->lv.at(lam)->n_sur > 0;
     const bool fork = lam >= kForkLevel && op->side;
     // stored interface rows are built (once) on s, before either stream reads them
     face_stencils(op->mesh->m, lam, s);
@@ -506,9 +521,14 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
         TS_REQUIRE(mesh && p && out, TS_EINVAL, "null argument");
         TS_REQUIRE(max_level >= 2 && max_level <= 9, TS_EINVAL, "max_level must be in 2..9");
         TS_REQUIRE(p->method == TS_IFEM || p->method == TS_LSQP || p->method == TS_IPOLY ||
-                       p->method == TS_LSQP_SYM,
+                       p->method == TS_LSQP_SYM || p->method == TS_CONS,
                    TS_EINVAL, "bad method");
-        if (p->method != TS_IFEM) {
+        if (p->method == TS_CONS) {
+            TS_REQUIRE(p->center == TS_CENTER_POLY || p->center == TS_CENTER_ROWSUM, TS_EINVAL,
+                       "bad centre mode");
+            TS_REQUIRE(!p->face_surrogate && !(p->fallback_tol > 0), TS_EINVAL,
+                       "the constant stencil takes no face surrogate and no fallback check");
+        } else if (p->method != TS_IFEM) {
             TS_REQUIRE(p->q >= 1 && p->q <= 4, TS_EINVAL, "degree q must be in 1..4");
             TS_REQUIRE(p->method != TS_IPOLY || p->q == 2, TS_EINVAL, "IPOLY is defined for q = 2");
             TS_REQUIRE(p->center == TS_CENTER_POLY || p->center == TS_CENTER_ROWSUM, TS_EINVAL,
@@ -522,7 +542,8 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             // the symmetric surrogate defines the centre weight by the row sum
             if (p->method == TS_LSQP_SYM) op->p.center = TS_CENTER_ROWSUM;
             op->max_level = max_level;
-            op->mq = p->method == TS_IFEM ? 0 : mq_of(p->q);
+            if (p->method == TS_CONS) op->p.q = 0;  // degree-0 "polynomials"
+            op->mq = p->method == TS_IFEM ? 0 : mq_of(op->p.q);
             for (int lam = 2; lam <= max_level; lam++) setup_level(op, lam, S(s));
             TS_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
             TS_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));

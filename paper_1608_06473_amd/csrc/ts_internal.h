@@ -338,6 +338,7 @@ void launch_coords(const Mesh& M, int lam, double* xyz, hipStream_t s);
 void launch_rhs(const Mesh& M, int lam, int kind, const double* dpar, int npar, double* f,
                 hipStream_t s);
 void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s);
+void launch_cons_stencils(const Mesh& M, int lam, double* coef, hipStream_t s);
 // symmetric surrogate: pair fits at the edge midpoints, translated to the 15
 // per-direction polynomials [nt][15][mq] (centre: minus the sum)
 void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* B, int nt,

@@ -1,6 +1,6 @@
 """Discretisation error over levels, macro meshes and stencil schemes on the
 GPU: an analogue of the paper's study of the refinement level, the macro mesh
-size H and the polynomial degree q (Sec. 4.2, Tab. hHstudy), on the
+size H and the polynomial degree q (Sec. 4.1, Tab. hHstudy), on the
 cubed-sphere shells of 36, 288 and 2,304 macros (the paper's meshes are not
 available).
 
@@ -13,7 +13,7 @@ e = (sum_I V_I (u(x_I) - u_I)^2)^(1/2) over the unique nodes, V_I a quarter
 of the volume of the node's fine tetrahedra (the consistent mass matrix
 applied to the constant 1).  Schemes: the exact element-wise operator
 (IFEM), LSQP of degree 1..4 with sampling j = 2, IPOLY (q = 2), and double
-discretisation with LSQP q = 2 (Sec. 4.1).
+discretisation with LSQP q = 2 (Sec. 4 introduction).
 
     python -m paper_1608_06473_amd.study [--meshes 36,288,2304] [--levels 3-6]
 """

@@ -45,7 +45,8 @@ def sweep_at_samples(O, N, f, x0, samples, **kw):
 
 def sample_free_nodes(O, N, rng, n_vol, n_lower, deep=0):
     """Random free nodes: n_vol interior nodes of random macros (at least
-    `deep` steps inside), and n_lower free face / edge / vertex nodes."""
+    `deep` steps inside), n_lower free face / edge / vertex nodes, and every
+    free macro vertex (too few to be drawn at random)."""
     out = []
     while len(out) < n_vol:
         t = int(rng.integers(0, O.nt))
@@ -59,4 +60,5 @@ def sample_free_nodes(O, N, rng, n_vol, n_lower, deep=0):
     if free_lower.size and n_lower:
         out += [int(u) for u in rng.choice(free_lower, size=min(n_lower, free_lower.size),
                                            replace=False)]
-    return np.array(out, dtype=np.int64)
+    out += [int(u) for u in np.flatnonzero(~dmask[:O.nv])]
+    return np.unique(np.array(out, dtype=np.int64))

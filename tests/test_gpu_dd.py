@@ -1,4 +1,4 @@
-"""Double discretisation (Sec. 4.1) through the C ABI vs the oracle.
+"""Double discretisation (Sec. 4 introduction) through the C ABI vs the oracle.
 
 The cycle smooths with the surrogate and computes every residual with the
 exact element-wise rows; the solve stops on the relative update.  The oracle's
@@ -109,7 +109,7 @@ def test_dd_requires_fp64(ts):
 
 
 def test_dd_keeps_the_fem_error_order(ts):
-    # Sec. 4.2 (the study of the error over refinement levels): on the
+    # Sec. 4.1 (the study of the error over refinement levels): on the
     # 288-macro shell the pure surrogate's error to the manufactured solution
     # stops decaying like h^2, while the mixed scheme stays on the Galerkin
     # solution's error.  Error: sum over nodes of V_I (u_exact - u_I)^2, V_I a

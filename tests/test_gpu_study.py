@@ -1,4 +1,4 @@
-"""The discretisation-error study (Sec. 4.2, Tab. hHstudy analogue) on the
+"""The discretisation-error study (Sec. 4.1, Tab. hHstudy analogue) on the
 288-macro shell at levels 4 and 5: the trends the paper reports.
 
 - the exact operator converges like h^2 (error ratio about 4 per level);

@@ -1,4 +1,4 @@
-"""The symmetric surrogate (TS_LSQP_SYM, the remark at the end of Sec. 3.3)
+"""The symmetric surrogate (TS_LSQP_SYM, the remark at the end of Sec. 3.4)
 through the C ABI vs the oracle.
 
 Each side fits on its own (GPU: FP64 normal equations of the seven pair

@@ -570,7 +570,7 @@ def test_load_vector_closed_forms_on_affine_macro(orc):
 
 
 # --------------------------------------------------------------------------
-# solver (Sec. 4.1): V-cycle, coarse solve and O(h^2) convergence
+# solver (Sec. 4 introduction: V-cycle, coarse solve; Sec. 4.1: O(h^2) convergence)
 # --------------------------------------------------------------------------
 
 def test_vcycle_solves_to_discrete_solution(orc):
@@ -675,7 +675,7 @@ def test_fallback_rows_are_ifem_rows(orc):
 
 
 # ---------------------------------------------------------------------------
-# double discretisation (Sec. 4.1): surrogate smoothing, exact residuals,
+# double discretisation (Sec. 4 introduction): surrogate smoothing, exact residuals,
 # stop on the update
 
 
@@ -722,7 +722,7 @@ def dd_runs(orc):
 
 
 def test_dd_recovers_most_of_the_fem_error(orc, dd_runs):
-    # Sec. 4.2: the mixed scheme moves the error of the surrogate solution
+    # Sec. 4.1: the mixed scheme moves the error of the surrogate solution
     # most of the way back to that of the exact Galerkin solution
     e = dd_runs["err"]
     assert e["ifem"] < e["dd"] < e["lsqp"]
@@ -730,7 +730,7 @@ def test_dd_recovers_most_of_the_fem_error(orc, dd_runs):
 
 
 def test_dd_residuals_stall_while_updates_vanish(orc, dd_runs):
-    # Sec. 4.1 / 4.2: the two operators compete, so neither residual goes to
+    # Sec. 4 introduction and Sec. 4.1: the two operators compete, so neither residual goes to
     # zero at the fixed point; the updates do (geometrically).  A cycle that
     # smoothed with L would drive ||f - L u|| to zero, one whose residual used
     # L~ would drive ||f - L~ u|| to zero.
@@ -829,7 +829,7 @@ def test_face_surrogate_row_sums_and_degree(orc):
 
 
 # ---------------------------------------------------------------------------
-# symmetric surrogate (remark at the end of Sec. 3.3): one polynomial per
+# symmetric surrogate (remark at the end of Sec. 3.4): one polynomial per
 # edge direction, evaluated at the edge midpoint; centre from the row sum
 
 # the 15 stencil directions (i, j, k) in the library's order

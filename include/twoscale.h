@@ -250,6 +250,22 @@ int ts_prolongate_add(ts_op *op, int level, int dtype, const void *uc, void *uf,
  * deterministic (fixed reduction order). */
 int ts_norm2(ts_mesh *mesh, int level, int dtype, const void *x, double *out, ts_stream s);
 
+/* ts_norm2 without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and reduction order as ts_norm2, so
+ * the same bits; the norm is written to the device double *out (caller's
+ * memory) asynchronously on s, and nothing is synchronised or copied to the
+ * host.  The partial sums go to a fixed device array of the library (8 MiB
+ * per GPU, kept until the process ends): TS_EINVAL if the level needs more
+ * than its 2^20 partial sums (a message gives both counts), if the level has
+ * not been built on the mesh yet (ts_layout builds it), or if the mesh's
+ * device is not the current one.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race and
+ * must be ordered by the caller.  No entry of the array needs clearing: each
+ * call writes every entry it reads. */
+int ts_norm2_noalloc(ts_mesh *mesh, int level, int dtype, const void *x, double *out,
+                     ts_stream s);
+
 /* ---- multigrid (Sec. 4 introduction: V(3,3) with Gauss-Seidel smoothing) --
  * Coarsest level 2 is solved exactly in FP64 with the inverse of its IFEM
  * matrix (computed on the device at creation).  Workspace owned by the

@@ -87,6 +87,8 @@ _SIGS = {
     "ts_prolongate_add": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     "ts_norm2": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ts_norm2_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
     "ts_solver_create": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "ts_solver_destroy": (C.c_int, [C.c_void_p]),
     "ts_vcycle": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -259,6 +261,12 @@ def ts_norm2(mesh, level, dtype, x, stream=None):
     out = C.c_double()
     _check(lib().ts_norm2(mesh, level, dtype, _ptr(x), C.byref(out), _stream(stream)))
     return out.value
+
+
+def ts_norm2_noalloc(mesh, level, dtype, x, out, stream=None):
+    """The norm into the device tensor out (one float64), no allocation."""
+    return _check(lib().ts_norm2_noalloc(mesh, level, dtype, _ptr(x), _ptr(out),
+                                         _stream(stream)))
 
 
 def ts_solver_create(op, level, nu1=3, nu2=3, max_cycles=60, precision=TS_F64, rtol=1e-10,

@@ -7,6 +7,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "ts_internal.h"
 #include "ts_face.h"
@@ -352,6 +354,48 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         if (b0 + t < n) v += p[b0 + t];
     const double s = block_sum(v);
     if (threadIdx.x == 0) out[blockIdx.x] = root ? sqrt(s) : s;
+}
+
+// ---------------------------------------------------------------- norm
+// without allocation
+//
+// The partial sums of the allocation-free norm live in a fixed device array
+// of this file, one copy per GPU that loads the library (held until the
+// process ends).  Host code never passes the array's name to a kernel (in
+// host code it is only a stand-in for the symbol): the device address of each
+// GPU's copy is looked up once, with that GPU current, and kept per device.
+constexpr int64_t kNormScratch = (int64_t)1 << 20;  // doubles (8 MiB)
+static __device__ __align__(256) double scratch[kNormScratch];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+static double* scratch_ptr(int dev) {
+    TS_REQUIRE(dev >= 0 && dev < 64, TS_EINVAL, "device id out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        TS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        TS_REQUIRE(p != nullptr, TS_EHIP, "no device address for the norm scratch array");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// the same kernels as ts_norm2 (so bitwise the same result), their partial
+// sums in the fixed array; the norm goes to the device double *out
+void norm2_noalloc(const Mesh& M, int lam, int dtype, const void* x, double* out,
+                   hipStream_t s) {
+    int dev = -1;
+    TS_HIP(hipGetDevice(&dev));
+    TS_REQUIRE(dev == M.device, TS_EINVAL, "the mesh's device must be the current device");
+    TS_REQUIRE(M.levels.count(lam), TS_EINVAL,
+               "level not built on this mesh (ts_layout builds it; this call allocates nothing)");
+    const int64_t need = norm_partial_count(M, lam);
+    TS_REQUIRE(need <= kNormScratch, TS_EINVAL,
+               "the norm needs " + std::to_string(need) + " partial sums, more than the " +
+                   std::to_string(kNormScratch) + " of the allocation-free variant");
+    launch_norm2_free(M, lam, dtype, x, scratch_ptr(dev), out, s);
 }
 
 static int64_t volume_partials(const Mesh& M, int lam) {

@@ -678,6 +678,15 @@ int ts_norm2(ts_mesh* mesh, int level, int dtype, const void* x, double* out, ts
     });
 }
 
+int ts_norm2_noalloc(ts_mesh* mesh, int level, int dtype, const void* x, double* out,
+                     ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(mesh && x && out, TS_EINVAL, "null argument");
+        check_dtype(dtype);
+        norm2_noalloc(mesh->m, level, dtype == TS_F64 ? TS_F64 : TS_F32, x, out, S(s));
+    });
+}
+
 int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver** out) {
     return guarded([&] {
         check_level(op, level);

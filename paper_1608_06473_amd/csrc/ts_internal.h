@@ -330,6 +330,7 @@ void launch_axpy(double a, const void* x, int dx, double* y, int64_t n, hipStrea
 double norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
                   hipStream_t s);  // synchronising
 int64_t norm_partial_count(const Mesh& M, int lam);
+void norm2_noalloc(const Mesh& M, int lam, int dtype, const void* x, double* out, hipStream_t s);
 void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double* partial,
                        double* out, hipStream_t s);
 void launch_canon_to_block(const Mesh& M, int lam, const double* c, double* b, hipStream_t s);

@@ -198,12 +198,20 @@ class Server:
         peak_used = 0
         peak_dev = 0
         occ_area = 0.0
+        occ_level = collections.defaultdict(float)  # time-weighted active count per level
+        used_area = 0.0  # time-weighted admitted bytes
+        dev_samples = []  # (time, library device bytes), sampled at most every 50 ms
         n_active = 0
         t0 = time.perf_counter()
         t_last = 0.0
         while pending or waiting or to_setup or setting_up or any(active.values()):
             now = time.perf_counter() - t0
             occ_area += n_active * (now - t_last)
+            for lvl, lst in active.items():
+                occ_level[lvl] += len(lst) * (now - t_last)
+            used_area += used * (now - t_last)
+            if not dev_samples or now - dev_samples[-1][0] >= 0.05:
+                dev_samples.append((now, ts_device_bytes()))
             t_last = now
             while pending and pending[0].t <= now:
                 waiting.append(pending.popleft())
@@ -301,6 +309,14 @@ class Server:
             torch.cuda.synchronize()
         t_end = time.perf_counter() - t0
         summ = summarize(reqs, t_end, occ_area, peak_used, peak_dev)
+        summ["mean_active_by_level"] = {int(l): round(a / max(t_end, 1e-9), 2)
+                                        for l, a in sorted(occ_level.items())}
+        summ["mean_admitted_gb"] = round(used_area / max(t_end, 1e-9) / 2 ** 30, 3)
+        if dev_samples:
+            b = np.array([d for _, d in dev_samples], dtype=np.float64)
+            summ["library_gb_over_time"] = {"samples": len(dev_samples),
+                                            "mean": round(float(b.mean()) / 2 ** 30, 3),
+                                            "max": round(float(b.max()) / 2 ** 30, 3)}
         summ["levels_shared"] = self.shared
         return reqs, summ
 

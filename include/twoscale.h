@@ -161,6 +161,15 @@ const char *ts_last_error(void);
 int ts_mesh_create(const double *vtx, int64_t nv, const int64_t *tet, int64_t nt, int geom,
                    ts_mesh **out);
 int ts_mesh_destroy(ts_mesh *mesh);
+/* Check that the mesh is a shell r_in <= |x| <= r_out (Sec. 2.1: the domain
+ * of the model problem, whose boundary is the two spheres): every vertex
+ * lies within [r_in - tol, r_out + tol], and every face of the mesh boundary
+ * (a face of one macro only) has its three vertices on the same sphere,
+ * | |v| - r | <= tol for r = r_in or r = r_out.  Host only, no device work.
+ * TS_EINVAL with the first offending vertex or face in ts_last_error().
+ * ts_mesh_create does not require it (TS_GEOM_AFFINE meshes need not be
+ * shells). */
+int ts_mesh_check_shell(const ts_mesh *mesh, double r_in, double r_out, double tol);
 /* A mesh with the connectivity of `like` and its own vertex coordinates (vtx:
  * nv x 3 host doubles, copied).  The levels already built on `like` (index
  * lists, tiles, lane orders: everything that depends on the connectivity
@@ -182,14 +191,16 @@ int ts_mesh_create_like(const ts_mesh *like, const double *vtx, ts_mesh **out);
 int ts_mesh_set_vertices(ts_mesh *mesh, const double *vtx);
 int ts_layout(ts_mesh *mesh, int level, ts_layout_info *out);
 
-/* canonical <-> block conversions of float64 device vectors.  to_block zeroes
+/* Layout helpers (Sec. 2.3: the nodes of a refined macro and their
+ * primitives; the canonical order numbers each unique node once).
+ * canonical <-> block conversions of float64 device vectors.  to_block zeroes
  * Dirichlet slots; to_canon reads the first copy of every node. */
 int ts_canon_to_block(ts_mesh *mesh, int level, const double *canon, double *block,
                       ts_stream s);
 int ts_block_to_canon(ts_mesh *mesh, int level, const double *block, double *canon,
                       ts_stream s);
-/* blended coordinates of every block slot: xyz is 3 * vec_len doubles
- * (slot-major, x y z). */
+/* blended coordinates of every block slot (Sec. 2.2: x = Phi_T(Psi_T(.)) of
+ * the fine node): xyz is 3 * vec_len doubles (slot-major, x y z). */
 int ts_node_coords(ts_mesh *mesh, int level, double *xyz, ts_stream s);
 
 /* Load vector f_l = M_l I_l f (Sec. 2.2 eq. algebraic with the consistent P1
@@ -246,8 +257,10 @@ int ts_smooth(ts_op *op, int level, int dtype, const void *f, void *u, int sweep
  * space P and its transpose R = P^T (Dirichlet rows 0). */
 int ts_restrict(ts_op *op, int level, int dtype, const void *rf, void *rc, ts_stream s);
 int ts_prolongate_add(ts_op *op, int level, int dtype, const void *uc, void *uf, ts_stream s);
-/* sqrt(sum over free nodes of x^2), each node once; synchronous,
- * deterministic (fixed reduction order). */
+/* sqrt(sum over free nodes of x^2), each node once: the Euclidean norm of
+ * the coefficient vector in the stopping test of the solver (Sec. 4
+ * introduction: relative residual); synchronous, deterministic (fixed
+ * reduction order). */
 int ts_norm2(ts_mesh *mesh, int level, int dtype, const void *x, double *out, ts_stream s);
 
 /* ts_norm2 without any allocation, for callers that cannot allocate device

@@ -65,6 +65,7 @@ _SIGS = {
     "ts_last_error": (C.c_char_p, []),
     "ts_mesh_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     "ts_mesh_destroy": (C.c_int, [C.c_void_p]),
+    "ts_mesh_check_shell": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
     "ts_mesh_set_vertices": (C.c_int, [C.c_void_p, C.c_void_p]),
     "ts_mesh_create_like": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_layout": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
@@ -166,6 +167,10 @@ def ts_mesh_create(vtx, tet, geom=TS_GEOM_SHELL):
 
 def ts_mesh_destroy(h):
     return _check(lib().ts_mesh_destroy(h))
+
+
+def ts_mesh_check_shell(h, r_in, r_out, tol=1e-12):
+    return _check(lib().ts_mesh_check_shell(h, r_in, r_out, tol))
 
 
 def ts_mesh_create_like(like, vtx):
@@ -367,6 +372,11 @@ class Mesh:
         else:
             self.tet = np.ascontiguousarray(tet, dtype=np.int64)
             self.h = ts_mesh_create(self.vtx, self.tet, geom)
+
+    def check_shell(self, r_in, r_out, tol=1e-12):
+        """Raise TSError unless the mesh is a shell r_in <= |x| <= r_out whose
+        boundary faces lie on the two spheres."""
+        ts_mesh_check_shell(self.h, r_in, r_out, tol)
 
     def layout(self, level):
         return ts_layout(self.h, level)

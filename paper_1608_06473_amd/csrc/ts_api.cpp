@@ -410,6 +410,43 @@ int ts_mesh_create(const double* vtx, int64_t nv, const int64_t* tet, int64_t nt
     });
 }
 
+int ts_mesh_check_shell(const ts_mesh* mesh, double r_in, double r_out, double tol) {
+    return guarded([&] {
+        TS_REQUIRE(mesh, TS_EINVAL, "null mesh");
+        TS_REQUIRE(std::isfinite(r_in) && std::isfinite(r_out) && 0.0 < r_in && r_in < r_out,
+                   TS_EINVAL, "radii must satisfy 0 < r_in < r_out");
+        TS_REQUIRE(tol >= 0.0 && tol < 0.5 * (r_out - r_in), TS_EINVAL, "bad tolerance");
+        const Mesh& M = mesh->m;
+        auto radius = [&](int64_t v) {
+            const double* p = &M.vtx[3 * v];
+            return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        };
+        for (int64_t v = 0; v < M.nv; v++) {
+            const double r = radius(v);
+            if (r < r_in - tol || r > r_out + tol)
+                throw Error{TS_EINVAL, "vertex " + std::to_string(v) + " at radius " +
+                                           std::to_string(r) + " lies outside the shell"};
+        }
+        // every face of the mesh boundary (one adjacent macro) lies on one of
+        // the two spheres: all three vertices at r_in, or all three at r_out
+        for (int64_t f = 0; f < M.nf; f++) {
+            if (M.f_tets[f].size() != 1) continue;
+            int on_in = 0, on_out = 0;
+            for (int a = 0; a < 3; a++) {
+                const double r = radius(M.faces[f][a]);
+                on_in += fabs(r - r_in) <= tol;
+                on_out += fabs(r - r_out) <= tol;
+            }
+            if (on_in != 3 && on_out != 3)
+                throw Error{TS_EINVAL, "boundary face " + std::to_string(f) + " (vertices " +
+                                           std::to_string(M.faces[f][0]) + ", " +
+                                           std::to_string(M.faces[f][1]) + ", " +
+                                           std::to_string(M.faces[f][2]) +
+                                           ") does not lie on the sphere r_in or r_out"};
+        }
+    });
+}
+
 int ts_mesh_destroy(ts_mesh* mesh) {
     return guarded([&] { delete mesh; });
 }

@@ -145,6 +145,7 @@ class Server:
                     self.template.layout(lam)
                     self.built.add(lam)
             r.mesh = Mesh(vtx, tet, like=self.template)
+        r.mesh.check_shell(r.r_in, 1.0)
         r.op = Operator(r.mesh, r.level, method=TS_LSQP, q=self.q, sample_j=2,
                         fallback_tol=self.fallback_tol, stream=r.stream)
         r.sv = Solver(r.op, r.level, precision=self.precision, rtol=self.rtol,

@@ -96,8 +96,13 @@ def test_level7_fp16_weight_apply_sampled_volume_rows(ts):
     half precision on coefficients scaled to order one (d0 + d1 z + d2 z^2
     by Horner: the rounded coefficients, z and two roundings give at most
     about 5 u_h of the weight's magnitude, u_h = 2^-11), and the row is a
-    15-term FP32 sum with |x| <= 1.  With the centre weight about the sum of
-    the others, the row error stays below 15 * 3 u_h max_w |s_w|."""
+    15-term FP32 sum with |x| <= 1.  The weights vary by tens of percent
+    across a macro, so d1 z and d2 z^2 are small next to d0: the rounded
+    coefficient d0 and the final rounding dominate, about 2 u_h |s_w| per
+    weight.  With x ~ U[-1, 1] the 15 errors add with random signs, RMS
+    2 sqrt(15) u_h max|s| E|x| (E|x| = 1/2, so about 3.9); the bound takes 4
+    times that for the largest of 3,000 rows: 15.5 u_h max_w |s_w| (the
+    measured maximum is 1.7, the worst case with aligned signs 30)."""
     import oracle
     G, O = pair("shell288")
     lam, N = 7, 128
@@ -121,5 +126,5 @@ def test_level7_fp16_weight_apply_sampled_volume_rows(ts):
                      for t, i, j, k in nodes])
     ratio = np.abs(y16[rows] - yo) / (2.0 ** -11 * smax)
     print("FP16-weight apply: max |y16 - y| / (u_h max|s|) = %.2f" % ratio.max())
-    assert ratio.max() <= 45.0
+    assert ratio.max() <= 15.5
     assert ratio.max() > 0.0  # the half-precision evaluation is in effect

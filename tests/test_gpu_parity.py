@@ -347,3 +347,25 @@ def test_bad_arguments(ts):
     x = G.zeros(3)
     with pytest.raises(ts.TSError):
         ts.ts_apply(op.h, 5, ts.TS_F64, x, G.zeros(3))
+
+
+def test_mesh_shell_check(ts):
+    # Sec. 2.1: the domain is the shell between two spheres; the check finds
+    # a vertex outside the radii and a boundary face off both spheres
+    v, t = inputs.shell288()
+    G = ts.Mesh(v, t)
+    G.check_shell(0.55, 1.0)
+    with pytest.raises(ts.TSError) as e:
+        G.check_shell(0.6, 1.0)
+    assert e.value.code == ts.TS_EINVAL and "outside the shell" in str(e.value)
+    with pytest.raises(ts.TSError) as e:
+        G.check_shell(0.5, 1.0)
+    assert "does not lie on the sphere" in str(e.value)
+    # one macro of the shell is a sector: its side faces are on neither sphere
+    vs, tsg = inputs.single_macro()
+    with pytest.raises(ts.TSError) as e:
+        ts.Mesh(vs, tsg).check_shell(0.55, 1.0)
+    assert "does not lie on the sphere" in str(e.value)
+    with pytest.raises(ts.TSError) as e:
+        ts.Mesh(*inputs.reference_tet(), ts.TS_GEOM_AFFINE).check_shell(0.55, 1.0)
+    assert "outside the shell" in str(e.value)

@@ -26,8 +26,13 @@
 
 namespace ts {
 
+// three plane buffers (48 KiB of LDS at staging width 2) and a 3-wave
+// register budget: three workgroups per CU (with four buffers, 64 KiB, two)
 #ifndef TS_IFEM_WAVES
-#define TS_IFEM_WAVES 1
+#define TS_IFEM_WAVES 3
+#endif
+#ifndef TS_IFEM_NB
+#define TS_IFEM_NB 3
 #endif
 
 // The macro's vertices in ascending global-id order, held in registers for
@@ -72,6 +77,35 @@ struct OrderedGeom {
     }
 };
 
+// stiffness_row0 with the reciprocal of 6 |T| from the hardware estimate
+// and two Newton steps (each doubles the correct bits: full FP64 precision)
+// instead of a correctly rounded division, which costs about twice the
+// instructions; the rows differ from stiffness_row0's by a few ulps
+__device__ __forceinline__ void stiffness_row0_fast(const double* P0, const double* P1,
+                                                    const double* P2, const double* P3,
+                                                    double K[4]) {
+    const double a0 = P1[0] - P0[0], a1 = P1[1] - P0[1], a2 = P1[2] - P0[2];
+    const double b0 = P2[0] - P0[0], b1 = P2[1] - P0[1], b2 = P2[2] - P0[2];
+    const double c0 = P3[0] - P0[0], c1 = P3[1] - P0[1], c2 = P3[2] - P0[2];
+    const double g10 = b1 * c2 - b2 * c1, g11 = b2 * c0 - b0 * c2, g12 = b0 * c1 - b1 * c0;
+    const double g20 = c1 * a2 - c2 * a1, g21 = c2 * a0 - c0 * a2, g22 = c0 * a1 - c1 * a0;
+    const double g30 = a1 * b2 - a2 * b1, g31 = a2 * b0 - a0 * b2, g32 = a0 * b1 - a1 * b0;
+    const double g00 = -(g10 + g20 + g30), g01 = -(g11 + g21 + g31), g02 = -(g12 + g22 + g32);
+    const double det = a0 * g10 + a1 * g11 + a2 * g12;
+    const double d6 = 6.0 * fabs(det);
+    double sc = __builtin_amdgcn_rcp(d6);
+    sc = fma(fma(-d6, sc, 1.0), sc, sc);
+    sc = fma(fma(-d6, sc, 1.0), sc, sc);
+    K[0] = (g00 * g00 + g01 * g01 + g02 * g02) * sc;
+    K[1] = (g00 * g10 + g01 * g11 + g02 * g12) * sc;
+    K[2] = (g00 * g20 + g01 * g21 + g02 * g22) * sc;
+    K[3] = (g00 * g30 + g01 * g31 + g02 * g32) * sc;
+}
+
+#ifndef TS_IFEM_FAST_RCP
+#define TS_IFEM_FAST_RCP 1
+#endif
+
 template <typename T, int MODE, int R, int KPT>
 __global__ __launch_bounds__(VOL_THREADS) __attribute__((amdgpu_waves_per_eu(TS_IFEM_WAVES)))
 void k_ifem_lds(
@@ -98,7 +132,11 @@ void k_ifem_lds(
     const __amdgpu_buffer_rsrc_t rf = block_rsrc(f ? f + base : x + base, bbytes);
     const __amdgpu_buffer_rsrc_t rc = block_rsrc(xyz + 3 * base, 3 * B * (int64_t)sizeof(double));
 
-    constexpr int NB = 4;
+    // plane buffers: with four, the buffer of plane p is rewritten four
+    // planes later, after the barriers in between; with three (less LDS, a
+    // third workgroup per CU) a second barrier per plane keeps the next
+    // write behind this plane's reads
+    constexpr int NB = TS_IFEM_NB;
     __shared__ T bx[NB][KPT * VOL_THREADS];
     __shared__ double bp[NB][3][KPT * VOL_THREADS];
 
@@ -189,7 +227,10 @@ void k_ifem_lds(
                     const double P3[3] = {bp[lb[w3]][0][li[w3]], bp[lb[w3]][1][li[w3]],
                                           bp[lb[w3]][2][li[w3]]};
                     double K[4];
-                    stiffness_row0(P0, P1, P2, P3, K);
+                    if constexpr (TS_IFEM_FAST_RCP)
+                        stiffness_row0_fast(P0, P1, P2, P3, K);
+                    else
+                        stiffness_row0(P0, P1, P2, P3, K);
                     s[0] += K[0];
                     s[w1] += K[1];
                     s[w2] += K[2];
@@ -213,6 +254,7 @@ void k_ifem_lds(
         }
         c -= nb;
         qa -= 1;
+        if constexpr (NB == 3) __syncthreads();
     }
 }
 

@@ -275,42 +275,11 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, T v) {
 // Staging loads of one plane range: KPT consecutive entries per lane from
 // element g on; entries past the range are never used by a live step (and
 // read 0 past the block's end).
-#ifndef TS_STAGE_PAIR
-#define TS_STAGE_PAIR 0
-#endif
 template <typename T, int KPT>
 __device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rx, int g, T r[KPT]) {
-    if constexpr (TS_STAGE_PAIR && KPT % 2 == 0) {
-        // two adjacent entries per lane and load (entries 2 tid, 2 tid + 1 of
-        // each 2 * VOL_THREADS block): half the load instructions
-        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int s = 0; s < KPT; s += 2) {
-            const int e = g + 2 * (int)threadIdx.x + s * VOL_THREADS;
-            if constexpr (sizeof(T) == 8) {
-                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rx, e * 8, 0, 0);
-                r[s] = __builtin_bit_cast(double, u32x2{v.x, v.y});
-                r[s + 1] = __builtin_bit_cast(double, u32x2{v.z, v.w});
-            } else {
-                const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rx, e * 4, 0, 0);
-                r[s] = __builtin_bit_cast(float, v.x);
-                r[s + 1] = __builtin_bit_cast(float, v.y);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int s = 0; s < KPT; s++)
-            r[s] = bload<T>(rx, (g + (int)threadIdx.x + s * VOL_THREADS) * (int)sizeof(T));
-    }
-}
-// LDS slot of a lane's staged entry s (the order stage_load loads them in)
-template <int KPT>
-__device__ __forceinline__ int stage_slot(int tid, int s) {
-    if constexpr (TS_STAGE_PAIR && KPT % 2 == 0)
-        return 2 * tid + (s & 1) + (s >> 1) * 2 * VOL_THREADS;
-    else
-        return tid + s * VOL_THREADS;
+    for (int s = 0; s < KPT; s++)
+        r[s] = bload<T>(rx, (g + (int)threadIdx.x + s * VOL_THREADS) * (int)sizeof(T));
 }
 
 // WP: weight provider (SurrogateW or SurrogateHalfW), T: vector type, W:
@@ -448,7 +417,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
     for (int st = g0; st < g0 + G && st < R + 2; st++) {
         T* bb = buf[st % (2 * G)];
 #pragma unroll
-        for (int s2 = 0; s2 < KPT; s2++) bb[stage_slot<KPT>(tid, s2)] = pf[st % PF][s2];
+        for (int s2 = 0; s2 < KPT; s2++) bb[tid + s2 * VOL_THREADS] = pf[st % PF][s2];
         if (st + PF <= R + 1) stage_load<T, KPT>(rx, sg(st + PF), pf[st % PF]);
     }
     __syncthreads();

@@ -31,6 +31,7 @@ import argparse
 import collections
 import concurrent.futures as cf
 import json
+import sys
 import threading
 import time
 
@@ -38,7 +39,7 @@ import numpy as np
 
 from . import (TS_EINVAL, TS_ENOMEM, TS_F32, TS_F64, TS_LSQP, TS_OK, TS_RHS_BUMPS,
                TS_SOLVE_DONE, TS_SOLVE_READY, Mesh, Operator, Solver, TSError, inputs,
-               ts_device_bytes, ts_solve_batch_step, ts_solve_info)
+               ts_device_bytes, ts_rhs, ts_solve_batch_step, ts_solve_info)
 
 TOPOLOGIES = {
     # the 288-macro shell (faces split 2 x 2, two radial layers) scaled to the
@@ -52,17 +53,79 @@ N_MACROS = {"shell288": 288, "shell36": 36}
 def request_bytes(n_macros, level, precision=TS_F32):
     """Admission estimate of the device bytes of one request: caller vectors
     f, u (FP64), the outer residual, the FP32 correction pair and three
-    V-cycle vectors per level (FP32 or FP64), the stored interface stencils,
-    plus a fixed allowance for coefficients, lists and the coarse inverse."""
+    V-cycle vectors per level (FP32 or FP64), the stored interface rows of
+    every level, the nodal load values of the right-hand side (a set-up
+    temporary), plus a fixed allowance for coefficients, lists and the
+    coarse inverse."""
     def vec(lam):
         N = 2 ** lam
         return n_macros * (N + 1) * (N + 2) * (N + 3) // 6
+    def face_nodes(lam):  # about 1.8 interior faces per macro, (N-1)(N-2)/2 nodes each
+        N = 2 ** lam
+        return int(1.84 * n_macros) * (N - 1) * (N - 2) // 2
     per_level = 12 if precision != TS_F64 else 24
-    b = vec(level) * (16 + 8 + (8 if precision != TS_F64 else 0) + 8)
+    b = vec(level) * (16 + 8 + (8 if precision != TS_F64 else 0) + 8 + 8)
     for lam in range(2, level + 1):
-        b += vec(lam) * per_level
+        # cycle vectors, and the stored interface rows of the request's
+        # geometry (two 15-entry FP64 copies per interior-face node)
+        b += vec(lam) * per_level + face_nodes(lam) * 240
     return int(b + 32 * 2 ** 20)
 
+
+class Ledger:
+    """Device-memory accounting of the admitted requests and the admission
+    rule.
+
+    A request's estimate is held from admission until its release has
+    completed on the releasing thread, not merely been handed to it: freeing
+    device memory waits for the device, so releases can lag far behind
+    retirements, and memory counted as free before it is free lets the
+    admitted set outgrow the device.  Estimates of requests admitted but not
+    yet set up are not in a free-memory snapshot yet; the rule subtracts
+    them."""
+
+    def __init__(self, budget, reserve):
+        self.budget, self.reserve = budget, reserve
+        self.held = 0          # admitted, release not completed
+        self.unallocated = 0   # admitted, set-up not finished
+        self.releasing = []    # (future, bytes, seconds at hand-over)
+        self.peak = 0
+        self.release_s = []    # hand-over to completion, per release batch
+
+    def fits(self, b, free=None):
+        """Whether a request of b bytes may be admitted now; free: the
+        device's free bytes (a snapshot), or None to check the budget only."""
+        if self.held + b > self.budget:
+            return False
+        return free is None or free - self.unallocated >= b + self.reserve
+
+    def admit(self, b):
+        self.held += b
+        self.unallocated += b
+        self.peak = max(self.peak, self.held)
+
+    def set_up(self, b):
+        """The request's set-up has ended (its memory is allocated, or it
+        failed and holds what it allocated until released)."""
+        self.unallocated -= b
+
+    def release(self, fut, b, now):
+        self.releasing.append((fut, b, now))
+
+    def poll(self, now):
+        """Return the estimates of the releases that have completed."""
+        keep = []
+        for fut, b, t in self.releasing:
+            if fut.done():
+                fut.result()
+                self.held -= b
+                self.release_s.append(now - t)
+            else:
+                keep.append((fut, b, t))
+        self.releasing = keep
+
+    def idle(self):
+        return self.held == 0 and not self.releasing
 
 
 
@@ -95,12 +158,19 @@ class Server:
     inflight_work: budget of refinement iterations in flight, in level-7
     iterations (8^(level - 7) each); one iteration is always allowed;
     warm_levels: levels whose layout data are built at start-up (else on the
-    first request that needs them).
+    first request that needs them); reserve_bytes: device memory that must
+    stay free beside an admitted request's estimate (the runtime needs some
+    for its own queues, and the estimate is only an estimate); yield_level:
+    while any request of this
+    level or below is being set up or solved, requests of higher levels get
+    no new iterations (their kernels would otherwise sit between the small
+    requests' many short kernels on the shared hardware queues); None: off.
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
                  hbm_budget=64 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
-                 keep=(), gc_batch=8, inflight_work=2.0, warm_levels=()):
+                 keep=(), gc_batch=8, inflight_work=2.0, warm_levels=(), yield_level=None,
+                 reserve_bytes=16 * 2 ** 30):
         import torch
         self.torch = torch
         self.topology = topology
@@ -113,6 +183,8 @@ class Server:
         self.keep = set(keep)
         self.gc_batch = gc_batch
         self.inflight_work = inflight_work
+        self.yield_level = yield_level
+        self.reserve_bytes = reserve_bytes
         self.template = None  # the layout's mesh; its levels are shared
         self.built = set()
         if warm_levels:
@@ -128,7 +200,6 @@ class Server:
         # retired requests are released on a thread of their own: freeing
         # device memory waits for the device, and the scheduler must not
         self.reaper = cf.ThreadPoolExecutor(max_workers=1)
-        self.reaping = []
 
     # -- per request ---------------------------------------------------------
     def _setup(self, r):
@@ -151,9 +222,20 @@ class Server:
         r.sv = Solver(r.op, r.level, precision=self.precision, rtol=self.rtol,
                       max_cycles=self.max_cycles)
         params = inputs.gaussian_bumps(r.id, r.r_in, 1.0)
+        # The request's vectors come from the caching allocator's pool of this
+        # thread's current stream (the default stream, shared by all
+        # requests) and are only written on the request's stream.  Allocated
+        # on the request's stream, their blocks would, once freed, serve only
+        # that stream again, and the pools of the pooled streams would grow
+        # side by side until the device is full.  They are freed after the
+        # request's stream has finished with them (the solve is DONE).
+        n = r.mesh.layout(r.level).vec_len
+        r.f = torch.empty(n, dtype=torch.float64, device="cuda")
+        r.u = torch.empty(n, dtype=torch.float64, device="cuda")
         with torch.cuda.stream(r.stream):
-            r.f = r.mesh.rhs(r.level, TS_RHS_BUMPS, params, stream=r.stream)
-            r.u = r.mesh.zeros(r.level)
+            r.f.zero_()
+            r.u.zero_()
+            ts_rhs(r.mesh.h, r.level, TS_RHS_BUMPS, params, r.f, r.stream)
         r.sv.begin(r.f, r.u, r.stream)
         return r
 
@@ -179,14 +261,16 @@ class Server:
             r.sv = r.op = r.mesh = r.f = r.u = None
             r.stream = None
 
-    def _destroy(self, reqs):
-        self.reaping = [f for f in self.reaping if not f.done()]
-        self.reaping.append(self.reaper.submit(self._destroy_now, list(reqs)))
+    def _destroy(self, ledger, reqs, now):
+        if reqs:
+            ledger.release(self.reaper.submit(self._destroy_now, list(reqs)),
+                           sum(r.bytes for r in reqs), now)
 
     # -- loop ----------------------------------------------------------------
-    def run(self, trace):
+    def run(self, trace, log=None):
         """Serve the trace (list of dicts id, t, level, r_in) in wall-clock
-        time and return (requests, summary)."""
+        time and return (requests, summary).  log (optional): called with a
+        progress line every 25 retired requests."""
         torch = self.torch
         reqs = [Request(rec, self.n_macros, self.precision) for rec in trace]
         pending = collections.deque(sorted(reqs, key=lambda r: r.t))
@@ -195,14 +279,16 @@ class Server:
         setting_up = {}
         active = collections.defaultdict(list)
         grave = []
-        used = 0
-        peak_used = 0
+        ledger = Ledger(self.hbm_budget, self.reserve_bytes)
         peak_dev = 0
         occ_area = 0.0
         occ_level = collections.defaultdict(float)  # time-weighted active count per level
         used_area = 0.0  # time-weighted admitted bytes
         dev_samples = []  # (time, library device bytes), sampled at most every 50 ms
         n_active = 0
+        n_retired = 0
+        emptied = False
+        t_log = 0.0
         t0 = time.perf_counter()
         t_last = 0.0
         while pending or waiting or to_setup or setting_up or any(active.values()):
@@ -210,10 +296,20 @@ class Server:
             occ_area += n_active * (now - t_last)
             for lvl, lst in active.items():
                 occ_level[lvl] += len(lst) * (now - t_last)
-            used_area += used * (now - t_last)
+            used_area += ledger.held * (now - t_last)
             if not dev_samples or now - dev_samples[-1][0] >= 0.05:
                 dev_samples.append((now, ts_device_bytes()))
             t_last = now
+            ledger.poll(now)
+            if log and now - t_log >= 2.0:
+                t_log = now
+                log("%.1f s: %d of %d served, %d active, %d in set-up, %d waiting; admitted "
+                    "%.1f GB (%d releases pending); library %.1f GB, torch reserved %.1f GB, "
+                    "device free %.1f GB"
+                    % (now, n_retired, len(reqs), n_active, len(setting_up) + len(to_setup),
+                       len(waiting), ledger.held / 2 ** 30, len(ledger.releasing),
+                       ts_device_bytes() / 2 ** 30, torch.cuda.memory_reserved() / 2 ** 30,
+                       torch.cuda.mem_get_info()[0] / 2 ** 30))
             while pending and pending[0].t <= now:
                 waiting.append(pending.popleft())
             # admission in arrival order, by slot and memory
@@ -225,16 +321,29 @@ class Server:
                     self._fail(r, now, TS_ENOMEM, "request needs %d bytes, over the HBM "
                                "budget of %d" % (r.bytes, self.hbm_budget))
                     continue
-                if used + r.bytes > self.hbm_budget:
+                free = torch.cuda.mem_get_info()[0] if torch.cuda.is_available() else None
+                if not ledger.fits(r.bytes, free):
                     if grave:
-                        used -= sum(g.bytes for g in grave)
-                        self._destroy(grave)
+                        self._destroy(ledger, grave, now)
                         grave = []
                         continue
+                    idle = (n_active + len(setting_up) + len(to_setup) == 0 and ledger.idle())
+                    if idle and not emptied:
+                        # nothing of ours is in flight: return torch's cached
+                        # blocks to the device and look again
+                        torch.cuda.empty_cache()
+                        emptied = True
+                        continue
+                    if idle:
+                        waiting.popleft()
+                        self._fail(r, now, TS_ENOMEM, "not enough free device memory for "
+                                   "the request (%d bytes and a reserve of %d)"
+                                   % (r.bytes, self.reserve_bytes))
+                        continue
                     break
+                emptied = False
                 waiting.popleft()
-                used += r.bytes
-                peak_used = max(peak_used, used)
+                ledger.admit(r.bytes)
                 r.t_admit = now
                 to_setup.append(r)
             # set-ups run on the worker threads, smallest level first
@@ -245,6 +354,7 @@ class Server:
             # requests whose set-up finished join the active set
             for fut in [f for f in setting_up if f.done()]:
                 r = setting_up.pop(fut)
+                ledger.set_up(r.bytes)
                 err = fut.exception()
                 r.t_ready = time.perf_counter() - t0
                 if err is not None:
@@ -271,6 +381,7 @@ class Server:
                         grave.append(r)
                         n_active -= 1
                         progressed = True
+                        n_retired += 1
                         continue
                     still.append(r)
                     if st == TS_SOLVE_READY:
@@ -279,7 +390,14 @@ class Server:
                         inflight += 8.0 ** (r.level - 7)
                 active[lvl] = still
             batch = []
+            yl = self.yield_level
+            small = yl is not None and (
+                any(active[l] for l in active if l <= yl)
+                or any(q.level <= yl for q in setting_up.values())
+                or any(q.level <= yl for q in to_setup))
             for r in ready:  # already in priority order
+                if small and r.level > yl:
+                    break
                 w = 8.0 ** (r.level - 7)
                 if inflight > 0.0 and inflight + w > self.inflight_work:
                     break
@@ -296,20 +414,19 @@ class Server:
                 progressed = True
             if len(grave) >= self.gc_batch:
                 peak_dev = max(peak_dev, ts_device_bytes())
-                used -= sum(g.bytes for g in grave)
-                self._destroy(grave)
+                self._destroy(ledger, grave, time.perf_counter() - t0)
                 grave = []
             if not progressed:
                 time.sleep(50e-6)
         peak_dev = max(peak_dev, ts_device_bytes())
-        self._destroy(grave)
-        for fut in self.reaping:
+        self._destroy(ledger, grave, time.perf_counter() - t0)
+        for fut, _, _ in ledger.releasing:
             fut.result()
-        self.reaping = []
+        ledger.poll(time.perf_counter() - t0)
         if any(r.t_admit is not None for r in reqs):
             torch.cuda.synchronize()
         t_end = time.perf_counter() - t0
-        summ = summarize(reqs, t_end, occ_area, peak_used, peak_dev)
+        summ = summarize(reqs, t_end, occ_area, ledger.peak, peak_dev)
         summ["mean_active_by_level"] = {int(l): round(a / max(t_end, 1e-9), 2)
                                         for l, a in sorted(occ_level.items())}
         summ["mean_admitted_gb"] = round(used_area / max(t_end, 1e-9) / 2 ** 30, 3)
@@ -318,6 +435,10 @@ class Server:
             summ["library_gb_over_time"] = {"samples": len(dev_samples),
                                             "mean": round(float(b.mean()) / 2 ** 30, 3),
                                             "max": round(float(b.max()) / 2 ** 30, 3)}
+        if ledger.release_s:
+            summ["release_s"] = {"batches": len(ledger.release_s),
+                                 "mean": round(float(np.mean(ledger.release_s)), 3),
+                                 "max": round(float(np.max(ledger.release_s)), 3)}
         summ["levels_shared"] = self.shared
         return reqs, summ
 
@@ -326,6 +447,8 @@ class Server:
         self.reaper.shutdown(wait=True)
         self.template = None
         self.built = set()
+        if self.torch.cuda.is_available():
+            self.torch.cuda.empty_cache()
 
 
 def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
@@ -378,6 +501,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--inflight-work", type=float, default=2.0)
     ap.add_argument("--max-active", type=int, default=32)
+    ap.add_argument("--yield-level", type=int, default=None,
+                    help="hold higher levels while requests up to this level are in flight")
     args = ap.parse_args()
     from . import TS_F16W
     lo, hi = (int(v) for v in args.levels.split("-"))
@@ -386,9 +511,10 @@ def main():
                                  levels=tuple(range(lo, hi + 1)))
     srv = Server(topology=args.topology, precision=prec, rtol=args.rtol,
                  max_active=args.max_active, inflight_work=args.inflight_work,
+                 yield_level=args.yield_level,
                  warm_levels=tuple(range(lo, hi + 1)))
     try:
-        _, summ = srv.run(trace)
+        _, summ = srv.run(trace, log=lambda m: print(m, file=sys.stderr, flush=True))
     finally:
         srv.close()
     print(json.dumps(summ), flush=True)

@@ -62,3 +62,50 @@ def test_request_over_the_budget_is_rejected_alone():
     assert "HBM budget" in reqs[0].error
     assert summ["failed"] == 2 and summ["completed_ok"] == 0
     assert summ["failed_by_status"] == {str(TS_ENOMEM): 2}
+
+
+class _Fut:
+    def __init__(self):
+        self.ok = False
+
+    def done(self):
+        return self.ok
+
+    def result(self):
+        return None
+
+
+def test_memory_is_held_until_its_release_completes():
+    # a retired request's estimate stays held while the releasing thread
+    # works (freeing device memory waits for the device); only a completed
+    # release makes room for new admissions
+    from paper_1608_06473_amd.serve import Ledger
+    L = Ledger(budget=100, reserve=0)
+    L.admit(60)
+    L.set_up(60)
+    assert not L.fits(50)
+    fut = _Fut()
+    L.release(fut, 60, now=1.0)
+    L.poll(now=2.0)
+    assert L.held == 60 and not L.fits(50) and not L.idle()
+    fut.ok = True
+    L.poll(now=3.5)
+    assert L.held == 0 and L.fits(50) and L.idle()
+    assert L.release_s == [2.5] and L.peak == 60
+
+
+def test_admission_counts_requests_not_yet_set_up():
+    # a free-memory snapshot does not show requests admitted but not set up
+    # yet: a burst of admissions from one snapshot must not exceed it
+    from paper_1608_06473_amd.serve import Ledger
+    L = Ledger(budget=1000, reserve=10)
+    free = 100
+    assert L.fits(40, free)
+    L.admit(40)
+    assert L.fits(40, free)        # 40 + 40 + 10 <= 100
+    L.admit(40)
+    assert not L.fits(40, free)    # the third would overrun the snapshot
+    L.set_up(40)                   # set-up done: now part of the snapshot
+    L.set_up(40)
+    assert L.fits(40, free - 80 + 80)
+    assert not L.fits(40, free - 80)

@@ -289,6 +289,21 @@ int ts_norm2_noalloc(ts_mesh *mesh, int level, int dtype, const void *x, double 
  * surrogate keeps exact). */
 int ts_solver_create(ts_op *op, int level, const ts_solve_params *p, ts_solver **out);
 int ts_solver_destroy(ts_solver *sv);
+/* Moves a solver, its operator and its mesh to new vertex coordinates of the
+ * same connectivity (vtx: nv x 3 host doubles, copied), as if all three had
+ * been created anew for them: the blending geometry (Sec. 2.2), the
+ * surrogate fits, per-macro fallback flags and face fits of every level of
+ * the operator (Sec. 3), the stored interface rows and the coarse inverse
+ * are rebuilt on s, in the device buffers they have (a buffer is replaced
+ * only where a length changes, e.g. when macros switch between surrogate
+ * and element-wise volume rows).  For request loops that keep solvers
+ * resident and reuse them for problems on differently scaled shells.
+ * Synchronous.  The mesh must carry this operator only (TS_EINVAL
+ * otherwise), and no solve of the solver may be in progress (ts_solve_begin
+ * without TS_SOLVE_DONE: TS_EINVAL).  Non-finite coordinates: TS_ENONFINITE
+ * with nothing changed.  After any other failure the objects are in an
+ * undefined state and must be destroyed. */
+int ts_solver_set_vertices(ts_solver *sv, const double *vtx, ts_stream s);
 /* one V(nu1, nu2) cycle on L u = f at the solver's level, in place */
 int ts_vcycle(ts_solver *sv, int dtype, const void *f, void *u, ts_stream s);
 /* full solve: u (float64, initial guess on entry) until the FP64 relative

@@ -67,6 +67,7 @@ _SIGS = {
     "ts_mesh_destroy": (C.c_int, [C.c_void_p]),
     "ts_mesh_check_shell": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
     "ts_mesh_set_vertices": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "ts_solver_set_vertices": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_mesh_create_like": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ts_layout": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "ts_canon_to_block": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -183,6 +184,11 @@ def ts_mesh_create_like(like, vtx):
 def ts_mesh_set_vertices(h, vtx):
     v = np.ascontiguousarray(vtx, dtype=np.float64)
     return _check(lib().ts_mesh_set_vertices(h, v.ctypes.data_as(C.c_void_p)))
+
+
+def ts_solver_set_vertices(sv, vtx, stream=None):
+    v = np.ascontiguousarray(vtx, dtype=np.float64)
+    return _check(lib().ts_solver_set_vertices(sv, v.ctypes.data_as(C.c_void_p), _stream(stream)))
 
 
 def ts_layout(mesh, level):
@@ -522,6 +528,18 @@ class Solver:
 
     def step(self):
         ts_solve_step(self.h)
+
+    def set_vertices(self, vtx, stream=None):
+        """Move the solver, its operator and its mesh to new vertex
+        coordinates of the same connectivity, rebuilding every
+        geometry-dependent part in place (no solve may be in progress; the
+        mesh must carry this operator only)."""
+        v = np.ascontiguousarray(vtx, dtype=np.float64)
+        mesh = self.op.mesh
+        if v.shape != mesh.vtx.shape:
+            raise ValueError("vertex array of a different shape")
+        ts_solver_set_vertices(self.h, v, stream)
+        mesh.vtx = v
 
     def query(self, info=None):
         return ts_solve_query(self.h, info)

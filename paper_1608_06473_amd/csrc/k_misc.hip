@@ -288,11 +288,19 @@ void launch_axpy(double a, const void* x, int dx, double* y, int64_t n, hipStrea
 // Deterministic: fixed per-block tree sums into partial[], then one block
 // sums partial[] in a fixed order.
 
+template <int NT = 256>
 __device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[256];
+    // NT threads; the part above the largest power of two P <= NT is folded
+    // onto the first NT - P entries first
+    constexpr int P = NT >= 1024 ? 1024 : NT >= 512 ? 512 : NT >= 256 ? 256 : NT >= 128 ? 128 : 64;
+    __shared__ double sh[NT];
     sh[threadIdx.x] = v;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    if constexpr (NT > P) {
+        if ((int)threadIdx.x < NT - P) sh[threadIdx.x] += sh[threadIdx.x + P];
+        __syncthreads();
+    }
+    for (int st = P / 2; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
@@ -303,13 +311,13 @@ __device__ __forceinline__ double block_sum(double v) {
 // column's interior nodes in the tile's slab (the columns of the volume
 // kernel, in its apply order)
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x,
+__global__ __launch_bounds__(VOL_THREADS) void k_norm_volume(const T* __restrict__ x,
                                                      const int4* __restrict__ tiles,
                                                      const unsigned* __restrict__ lanes, int N,
                                                      int64_t B, double* __restrict__ partial) {
     const int tile = blockIdx.x, macro = blockIdx.y;
     const int k0 = tiles[tile].x;
-    const unsigned e = lanes[(size_t)tile * 256 + threadIdx.x];
+    const unsigned e = lanes[(size_t)tile * VOL_THREADS + threadIdx.x];
     double v = 0.0;
     if (e != 0xFFFFFFFFu) {
         const int i = (int)(e & 0xFFFFu), j = (int)(e >> 16);
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(256) void k_norm_volume(const T* __restrict__ x,
             idx += Ak * (Ak + 1) / 2 - j;
         }
     }
-    const double s = block_sum(v);
+    const double s = block_sum<VOL_THREADS>(v);
     if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
@@ -418,9 +426,9 @@ void launch_norm2_free(const Mesh& M, int lam, int dtype, const void* x, double*
     if (n1) {
         const dim3 g1((unsigned)L.n_lds_tiles, (unsigned)M.nt);
         if (dtype == TS_F64)
-            k_norm_volume<double><<<g1, 256, 0, s>>>((const double*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
+            k_norm_volume<double><<<g1, VOL_THREADS, 0, s>>>((const double*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
         else
-            k_norm_volume<float><<<g1, 256, 0, s>>>((const float*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
+            k_norm_volume<float><<<g1, VOL_THREADS, 0, s>>>((const float*)x, L.lds_tiles.p, L.ap_lanes.p, L.N, L.B, partial);
     }
     if (n2) {
         if (dtype == TS_F64)

@@ -115,9 +115,18 @@ static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vec
     lo.has_coef = true;
 }
 
+// Builds the level's geometry-dependent operator data; a level built before
+// (new vertex coordinates) is rebuilt in the buffers it has.
 static void setup_level(ts_op* op, int lam, hipStream_t s) {
     Mesh& M = op->mesh->m;
-    auto lo = std::make_unique<LevelOp>();
+    std::unique_ptr<LevelOp> lo;
+    auto it = op->lv.find(lam);
+    if (it != op->lv.end()) {
+        lo = std::move(it->second);
+        op->lv.erase(it);
+    } else {
+        lo = std::make_unique<LevelOp>();
+    }
     lo->lam = lam;
     M.level(lam);
     if (op->p.method == TS_CONS && lam >= 3) {
@@ -724,6 +733,34 @@ int ts_norm2_noalloc(ts_mesh* mesh, int level, int dtype, const void* x, double*
     });
 }
 
+namespace ts {
+
+// element-wise volume rows stop at level 8: a solve above it must keep
+// surrogate rows everywhere and take no exact residuals
+static void check_exact_rows(const ts_op* op, int level, bool dd) {
+    for (int lam = 9; lam <= level; lam++) {
+        TS_REQUIRE(!dd, TS_EINVAL, "double discretisation needs IFEM rows: level 8 at most");
+        TS_REQUIRE(uses_surrogate(op, lam) && op->lv.at(lam)->n_ifem == 0, TS_EINVAL,
+                   "IFEM volume rows (method or selective surrogate) are supported up to level 8");
+    }
+}
+
+// the solver's geometry-dependent data on s: the coarse inverse, and the
+// stored rows, coordinates and Gauss-Seidel scratch of every level the cycle
+// visits (built now rather than in a step); synchronous
+static void solver_geometry(ts_solver* sv, hipStream_t s) {
+    ts_op* op = sv->op;
+    coarse_setup(sv, s);
+    for (int lam = 3; lam <= sv->L; lam++) {
+        const bool ifem = sv->p.dd || !uses_surrogate(op, lam) || op->lv.at(lam)->n_ifem > 0;
+        warm_level(op, lam, ifem, s);
+        iface_tmp(op, lam);
+    }
+    TS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace ts
+
 int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver** out) {
     return guarded([&] {
         check_level(op, level);
@@ -735,13 +772,7 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
         check_dtype(p->precision);
         TS_REQUIRE(!p->dd || p->precision == TS_F64, TS_EINVAL,
                    "double discretisation runs in FP64 precision");
-        // element-wise volume rows stop at level 8: a solve above it must
-        // keep surrogate rows everywhere and take no exact residuals
-        for (int lam = 9; lam <= level; lam++) {
-            TS_REQUIRE(!p->dd, TS_EINVAL, "double discretisation needs IFEM rows: level 8 at most");
-            TS_REQUIRE(uses_surrogate(op, lam) && op->lv.at(lam)->n_ifem == 0, TS_EINVAL,
-                       "IFEM volume rows (method or selective surrogate) are supported up to level 8");
-        }
+        check_exact_rows(op, level, p->dd);
         auto* sv = new ts_solver();
         try {
             sv->op = op;
@@ -753,15 +784,7 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
             hipStream_t s = nullptr;
             TS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
             try {
-                coarse_setup(sv, s);
-                // stored rows, coordinates and Gauss-Seidel scratch of every
-                // level the cycle visits, built now rather than in a step
-                for (int lam = 3; lam <= level; lam++) {
-                    const bool ifem = p->dd || !uses_surrogate(op, lam) || op->lv.at(lam)->n_ifem > 0;
-                    warm_level(op, lam, ifem, s);
-                    iface_tmp(op, lam);
-                }
-                TS_HIP(hipStreamSynchronize(s));
+                solver_geometry(sv, s);
             } catch (...) {
                 (void)hipStreamDestroy(s);
                 throw;
@@ -790,6 +813,34 @@ int ts_solver_create(ts_op* op, int level, const ts_solve_params* p, ts_solver**
 
 int ts_solver_destroy(ts_solver* sv) {
     return guarded([&] { delete sv; });
+}
+
+int ts_solver_set_vertices(ts_solver* sv, const double* vtx, ts_stream s) {
+    return guarded([&] {
+        TS_REQUIRE(sv && vtx, TS_EINVAL, "null argument");
+        TS_REQUIRE(sv->state == 0 || sv->state == TS_SOLVE_DONE, TS_EINVAL,
+                   "a solve is in progress");
+        ts_op* op = sv->op;
+        ts_mesh* mesh = op->mesh;
+        TS_REQUIRE(mesh->ops.load() == 1, TS_EINVAL,
+                   "the mesh carries other operators than the solver's");
+        Mesh& M = mesh->m;
+        for (int64_t i = 0; i < 3 * M.nv; i++)
+            TS_REQUIRE(std::isfinite(vtx[i]), TS_ENONFINITE, "non-finite vertex coordinate");
+        std::vector<double> old(M.vtx);
+        M.vtx.assign(vtx, vtx + 3 * M.nv);
+        try {
+            build_geometry(M);
+        } catch (...) {
+            M.vtx.swap(old);
+            throw;
+        }
+        M.geo_gen++;  // stored coordinates and interface rows are rebuilt on use
+        sv->state = 0;
+        for (int lam = 2; lam <= op->max_level; lam++) setup_level(op, lam, S(s));
+        check_exact_rows(op, sv->L, sv->p.dd);
+        solver_geometry(sv, S(s));
+    });
 }
 
 int ts_vcycle(ts_solver* sv, int dtype, const void* f, void* u, ts_stream s) {

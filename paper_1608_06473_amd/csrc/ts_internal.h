@@ -54,7 +54,10 @@ struct DBuf {
         p = nullptr;
         n = 0;
     }
+    // keeps the buffer when it already holds count elements (rebuilds of
+    // geometry-dependent data reuse their memory); contents are undefined
     void alloc(size_t count) {
+        if (p && n == count) return;
         reset();
         if (count == 0) return;
         hipError_t e = hipMalloc(&p, count * sizeof(X));
@@ -206,7 +209,12 @@ struct Level {
 #define TS_VOL_WAVES_EU 3
 #endif
 constexpr int VOL_R = TS_VOL_R;  // planes per volume tile
-constexpr int VOL_THREADS = 256;
+// threads of a volume workgroup (one column each; a multiple of 64)
+#ifndef TS_VOL_THREADS
+#define TS_VOL_THREADS 256
+#endif
+constexpr int VOL_THREADS = TS_VOL_THREADS;
+static_assert(VOL_THREADS % 64 == 0 && VOL_THREADS <= 1024, "bad volume workgroup size");
 
 // Level data that depend on the vertex coordinates, owned by each mesh and
 // built on first use: the blended coordinates of every slot (element-wise

@@ -2,24 +2,30 @@
 
 Requests arrive at their trace times: a level, an inner radius, and a
 right-hand side of Gaussian bumps.  A request is admitted when it fits the
-HBM budget and a slot is free.  A worker thread then builds its mesh,
-surrogate operator and multigrid solver on the request's own stream, and
-enqueues the start of the solve (ts_solve_begin).  The scheduler thread polls
+HBM budget and a slot is free.  A worker thread then builds (or re-targets)
+its mesh, surrogate operator and multigrid solver on the solver's own stream,
+and enqueues the start of the solve (ts_solve_begin).  The scheduler thread polls
 every active solve without blocking (ts_solve_query) and enqueues the next
 refinement iteration of requests whose last one has finished, in one batched
 call (ts_solve_batch_step),
 smallest level first and, within a level, in arrival order, as long as the
-work in flight stays under a budget (an iteration at level l counts
-8^(l - 7), so about two level-7 iterations run at once while small requests
-pass them).  Work of many requests is therefore in flight on the
+work in flight stays under a budget (an iteration counts its unknowns
+relative to a level-7 iteration on the 288-macro shell, so about two of those
+run at once while small requests pass them).  Work of many requests is therefore in flight on the
 device at once, and requests arriving meanwhile join as slots and memory free
 up.  A request retires when its FP64 relative residual reaches the tolerance.
 
 Requests on one macro layout differ only in their radii, so the server
 keeps a template mesh of the layout whose levels (index lists, tiles, lane
-orders) are built once, on first need, and every request's mesh shares them
-(ts_mesh_create_like) with its own vertices; only the geometry-dependent data
-are built per request.
+orders) are built once, on first need, and every solver's mesh shares them
+(ts_mesh_create_like) with its own vertices.  Solvers stay resident in HBM:
+when a request retires, its solver (mesh, operator, multigrid state and
+vectors) serves the next request of the same level, moved to that request's
+shell in place (ts_solver_set_vertices rebuilds only the geometry-dependent
+data, in the buffers they have).  Freeing device memory waits for the whole
+device, so a solver is released only when the memory is needed for another
+level (the one idle the longest first), on a thread of its own, and its
+memory counts as used until the release has completed.
 
 Every request runs the same sequence of kernels on its own data whatever else
 is in flight (no atomics, fixed reduction order), so a result is bitwise the
@@ -92,12 +98,19 @@ class Ledger:
         self.peak = 0
         self.release_s = []    # hand-over to completion, per release batch
 
+    def shortfall(self, b, free=None, pending=False):
+        """Bytes missing for a request of b bytes (<= 0: it fits); free: the
+        device's free bytes (a snapshot), or None to check the budget only;
+        pending: count the releases in progress as done."""
+        pend = sum(x for _, x, _ in self.releasing) if pending else 0
+        s = self.held - pend + b - self.budget
+        if free is not None:
+            s = max(s, b + self.reserve - (free + pend - self.unallocated))
+        return s
+
     def fits(self, b, free=None):
-        """Whether a request of b bytes may be admitted now; free: the
-        device's free bytes (a snapshot), or None to check the budget only."""
-        if self.held + b > self.budget:
-            return False
-        return free is None or free - self.unallocated >= b + self.reserve
+        """Whether a request of b bytes may be admitted now."""
+        return self.shortfall(b, free) <= 0
 
     def admit(self, b):
         self.held += b
@@ -129,16 +142,39 @@ class Ledger:
 
 
 
+class Slot:
+    """A resident solver of one level: its stream, mesh, operator, solver and
+    the caller vectors f, u.  A slot serves one request at a time and, once
+    that request has retired, the next request of its level (the solver is
+    moved to the new shell in place)."""
+    __slots__ = ("level", "bytes", "stream", "mesh", "op", "sv", "f", "u", "t_idle")
+
+    def __init__(self, level, nbytes):
+        self.level, self.bytes = level, nbytes
+        self.stream = self.mesh = self.op = self.sv = self.f = self.u = None
+        self.t_idle = 0.0
+
+
+def request_work(n_macros, level):
+    """Work of one refinement iteration relative to one on the 288-macro
+    shell at level 7 (the ratio of the block sizes)."""
+    def vec(m, lam):
+        N = 2 ** lam
+        return m * (N + 1) * (N + 2) * (N + 3) // 6
+    return vec(n_macros, level) / vec(288, 7)
+
+
 class Request:
-    __slots__ = ("id", "t", "level", "r_in", "bytes", "t_admit", "t_ready", "t_done", "stream",
-                 "mesh", "op", "sv", "f", "u", "info", "status", "cycles", "rel", "u_host",
-                 "error")
+    __slots__ = ("id", "t", "level", "r_in", "bytes", "work", "t_admit", "t_ready", "t_done",
+                 "slot", "new", "info", "status", "cycles", "rel", "u_host", "error")
 
     def __init__(self, rec, n_macros, precision):
         self.id, self.t, self.level, self.r_in = rec["id"], rec["t"], rec["level"], rec["r_in"]
         self.bytes = request_bytes(n_macros, self.level, precision)
+        self.work = request_work(n_macros, self.level)
         self.t_admit = self.t_ready = self.t_done = None
-        self.stream = self.mesh = self.op = self.sv = self.f = self.u = None
+        self.slot = None
+        self.new = True  # its slot was created for it (not a resident one)
         self.info = ts_solve_info()
         self.status = None
         self.cycles = 0
@@ -155,10 +191,14 @@ class Server:
     FP64 refinement), TS_F16W or TS_F64; rtol: FP64 relative residual to
     reach; hbm_budget: bytes the admitted requests may use (estimate);
     max_active: slots; keep: ids whose solutions are copied to the host;
-    inflight_work: budget of refinement iterations in flight, in level-7
-    iterations (8^(level - 7) each); one iteration is always allowed;
+    inflight_work: budget of refinement iterations in flight, in units of a
+    level-7 iteration on the 288-macro shell (request_work); one iteration is
+    always allowed;
     warm_levels: levels whose layout data are built at start-up (else on the
-    first request that needs them); reserve_bytes: device memory that must
+    first request that needs them); resident: keep the solver of a retired
+    request resident and serve the next request of its level with it (moved
+    to the new shell in place, ts_solver_set_vertices) instead of building
+    and releasing one per request; reserve_bytes: device memory that must
     stay free beside an admitted request's estimate (the runtime needs some
     for its own queues, and the estimate is only an estimate); yield_level:
     while any request of this
@@ -168,9 +208,9 @@ class Server:
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
-                 hbm_budget=64 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
+                 hbm_budget=160 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
                  keep=(), gc_batch=8, inflight_work=2.0, warm_levels=(), yield_level=None,
-                 reserve_bytes=16 * 2 ** 30):
+                 reserve_bytes=16 * 2 ** 30, resident=True):
         import torch
         self.torch = torch
         self.topology = topology
@@ -195,6 +235,10 @@ class Server:
                 self.built.add(lam)
         self.tlock = threading.Lock()
         self.shared = 0       # requests whose levels were all built already
+        self.resident = resident
+        self.idle = collections.defaultdict(list)  # level -> idle resident solvers
+        self.reused = 0       # requests served by a resident solver
+        self.evicted = 0      # resident solvers released to make room
         self.setup_workers = setup_workers
         self.pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
         # retired requests are released on a thread of their own: freeing
@@ -204,39 +248,44 @@ class Server:
     # -- per request ---------------------------------------------------------
     def _setup(self, r):
         torch = self.torch
-        r.stream = torch.cuda.Stream()
         vtx, tet = TOPOLOGIES[self.topology](r.r_in)
-        with self.tlock:  # levels are built on the template once, under the lock
-            if self.template is None:
-                self.template = Mesh(vtx, tet)
-            if r.level in self.built:
-                self.shared += 1
-            for lam in range(2, r.level + 1):
-                if lam not in self.built:
-                    self.template.layout(lam)
-                    self.built.add(lam)
-            r.mesh = Mesh(vtx, tet, like=self.template)
-        r.mesh.check_shell(r.r_in, 1.0)
-        r.op = Operator(r.mesh, r.level, method=TS_LSQP, q=self.q, sample_j=2,
-                        fallback_tol=self.fallback_tol, stream=r.stream)
-        r.sv = Solver(r.op, r.level, precision=self.precision, rtol=self.rtol,
-                      max_cycles=self.max_cycles)
+        sl = r.slot
+        if not r.new:
+            # a resident solver of this level, moved to the request's shell
+            sl.sv.set_vertices(vtx, sl.stream)
+        else:
+            sl.stream = torch.cuda.Stream()
+            with self.tlock:  # levels are built on the template once, under the lock
+                if self.template is None:
+                    self.template = Mesh(vtx, tet)
+                if r.level in self.built:
+                    self.shared += 1
+                for lam in range(2, r.level + 1):
+                    if lam not in self.built:
+                        self.template.layout(lam)
+                        self.built.add(lam)
+                sl.mesh = Mesh(vtx, tet, like=self.template)
+            sl.op = Operator(sl.mesh, r.level, method=TS_LSQP, q=self.q, sample_j=2,
+                             fallback_tol=self.fallback_tol, stream=sl.stream)
+            sl.sv = Solver(sl.op, r.level, precision=self.precision, rtol=self.rtol,
+                           max_cycles=self.max_cycles)
+            # The vectors come from the caching allocator's pool of this
+            # thread's current stream (the default stream, shared by all
+            # slots) and are only written on the slot's stream.  Allocated on
+            # the slot's stream, their blocks would, once freed, serve only
+            # that stream again, and the pools of the pooled streams would
+            # grow side by side.  They are freed after the slot's stream has
+            # finished with them (its last solve is DONE).
+            n = sl.mesh.layout(r.level).vec_len
+            sl.f = torch.empty(n, dtype=torch.float64, device="cuda")
+            sl.u = torch.empty(n, dtype=torch.float64, device="cuda")
+        sl.mesh.check_shell(r.r_in, 1.0)
         params = inputs.gaussian_bumps(r.id, r.r_in, 1.0)
-        # The request's vectors come from the caching allocator's pool of this
-        # thread's current stream (the default stream, shared by all
-        # requests) and are only written on the request's stream.  Allocated
-        # on the request's stream, their blocks would, once freed, serve only
-        # that stream again, and the pools of the pooled streams would grow
-        # side by side until the device is full.  They are freed after the
-        # request's stream has finished with them (the solve is DONE).
-        n = r.mesh.layout(r.level).vec_len
-        r.f = torch.empty(n, dtype=torch.float64, device="cuda")
-        r.u = torch.empty(n, dtype=torch.float64, device="cuda")
-        with torch.cuda.stream(r.stream):
-            r.f.zero_()
-            r.u.zero_()
-            ts_rhs(r.mesh.h, r.level, TS_RHS_BUMPS, params, r.f, r.stream)
-        r.sv.begin(r.f, r.u, r.stream)
+        with torch.cuda.stream(sl.stream):
+            sl.f.zero_()
+            sl.u.zero_()
+            ts_rhs(sl.mesh.h, r.level, TS_RHS_BUMPS, params, sl.f, sl.stream)
+        sl.sv.begin(sl.f, sl.u, sl.stream)
         return r
 
     def _retire(self, r, now):
@@ -245,8 +294,8 @@ class Server:
         r.cycles = r.info.cycles
         r.rel = r.info.rel_residual
         if r.id in self.keep and r.status == TS_OK:
-            with self.torch.cuda.stream(r.stream):
-                r.u_host = r.u.cpu().numpy()
+            with self.torch.cuda.stream(r.slot.stream):
+                r.u_host = r.slot.u.cpu().numpy()
 
     @staticmethod
     def _fail(r, now, code, msg):
@@ -256,21 +305,21 @@ class Server:
         r.error = msg
 
     @staticmethod
-    def _destroy_now(reqs):
-        for r in reqs:
-            r.sv = r.op = r.mesh = r.f = r.u = None
-            r.stream = None
+    def _destroy_now(slots):
+        for sl in slots:
+            sl.sv = sl.op = sl.mesh = sl.f = sl.u = None
+            sl.stream = None
 
-    def _destroy(self, ledger, reqs, now):
-        if reqs:
-            ledger.release(self.reaper.submit(self._destroy_now, list(reqs)),
-                           sum(r.bytes for r in reqs), now)
+    def _destroy(self, ledger, slots, now):
+        if slots:
+            ledger.release(self.reaper.submit(self._destroy_now, list(slots)),
+                           sum(sl.bytes for sl in slots), now)
 
     # -- loop ----------------------------------------------------------------
     def run(self, trace, log=None):
         """Serve the trace (list of dicts id, t, level, r_in) in wall-clock
         time and return (requests, summary).  log (optional): called with a
-        progress line every 25 retired requests."""
+        progress line every 2 s."""
         torch = self.torch
         reqs = [Request(rec, self.n_macros, self.precision) for rec in trace]
         pending = collections.deque(sorted(reqs, key=lambda r: r.t))
@@ -303,16 +352,18 @@ class Server:
             ledger.poll(now)
             if log and now - t_log >= 2.0:
                 t_log = now
-                log("%.1f s: %d of %d served, %d active, %d in set-up, %d waiting; admitted "
-                    "%.1f GB (%d releases pending); library %.1f GB, torch reserved %.1f GB, "
-                    "device free %.1f GB"
+                log("%.1f s: %d of %d served, %d active, %d in set-up, %d waiting, %d resident "
+                    "idle; held %.1f GB (%d releases pending); library %.1f GB, torch reserved "
+                    "%.1f GB, device free %.1f GB"
                     % (now, n_retired, len(reqs), n_active, len(setting_up) + len(to_setup),
-                       len(waiting), ledger.held / 2 ** 30, len(ledger.releasing),
+                       len(waiting), sum(len(v) for v in self.idle.values()),
+                       ledger.held / 2 ** 30, len(ledger.releasing),
                        ts_device_bytes() / 2 ** 30, torch.cuda.memory_reserved() / 2 ** 30,
                        torch.cuda.mem_get_info()[0] / 2 ** 30))
             while pending and pending[0].t <= now:
                 waiting.append(pending.popleft())
-            # admission in arrival order, by slot and memory
+            # admission in arrival order: a resident solver of the request's
+            # level if one is idle, else a new one if the memory allows
             while waiting and n_active + len(setting_up) + len(to_setup) < self.max_active:
                 r = waiting[0]
                 if r.bytes > self.hbm_budget:
@@ -321,20 +372,37 @@ class Server:
                     self._fail(r, now, TS_ENOMEM, "request needs %d bytes, over the HBM "
                                "budget of %d" % (r.bytes, self.hbm_budget))
                     continue
+                if self.idle[r.level]:
+                    waiting.popleft()
+                    r.slot = self.idle[r.level].pop()
+                    r.new = False
+                    self.reused += 1
+                    r.t_admit = now
+                    to_setup.append(r)
+                    continue
                 free = torch.cuda.mem_get_info()[0] if torch.cuda.is_available() else None
                 if not ledger.fits(r.bytes, free):
                     if grave:
                         self._destroy(ledger, grave, now)
                         grave = []
                         continue
-                    idle = (n_active + len(setting_up) + len(to_setup) == 0 and ledger.idle())
-                    if idle and not emptied:
-                        # nothing of ours is in flight: return torch's cached
-                        # blocks to the device and look again
+                    lru = [sl for lst in self.idle.values() for sl in lst]
+                    if lru and ledger.shortfall(r.bytes, free, pending=True) > 0:
+                        # release the resident solver idle the longest
+                        sl = min(lru, key=lambda q: q.t_idle)
+                        self.idle[sl.level].remove(sl)
+                        self._destroy(ledger, [sl], now)
+                        self.evicted += 1
+                        continue
+                    busy = (n_active + len(setting_up) + len(to_setup) > 0
+                            or ledger.releasing or lru)
+                    if not busy and not emptied:
+                        # nothing of ours is in flight or resident: return
+                        # torch's cached blocks to the device and look again
                         torch.cuda.empty_cache()
                         emptied = True
                         continue
-                    if idle:
+                    if not busy:
                         waiting.popleft()
                         self._fail(r, now, TS_ENOMEM, "not enough free device memory for "
                                    "the request (%d bytes and a reserve of %d)"
@@ -343,6 +411,7 @@ class Server:
                     break
                 emptied = False
                 waiting.popleft()
+                r.slot = Slot(r.level, r.bytes)
                 ledger.admit(r.bytes)
                 r.t_admit = now
                 to_setup.append(r)
@@ -354,15 +423,16 @@ class Server:
             # requests whose set-up finished join the active set
             for fut in [f for f in setting_up if f.done()]:
                 r = setting_up.pop(fut)
-                ledger.set_up(r.bytes)
+                if r.new:
+                    ledger.set_up(r.bytes)
                 err = fut.exception()
                 r.t_ready = time.perf_counter() - t0
                 if err is not None:
                     # a failed set-up (device memory, non-finite data, ...)
-                    # ends this request only; its memory is released
+                    # ends this request only; its solver is released
                     code = err.code if isinstance(err, TSError) else TS_EINVAL
                     self._fail(r, r.t_ready, code, str(err))
-                    grave.append(r)
+                    grave.append(r.slot)
                     continue
                 active[r.level].append(r)
                 n_active += 1
@@ -375,10 +445,17 @@ class Server:
             for lvl in sorted(active):
                 still = []
                 for r in active[lvl]:
-                    st = r.sv.query(r.info)
+                    st = r.slot.sv.query(r.info)
                     if st == TS_SOLVE_DONE:
-                        self._retire(r, time.perf_counter() - t0)
-                        grave.append(r)
+                        t_done = time.perf_counter() - t0
+                        self._retire(r, t_done)
+                        if r.status == TS_OK and self.resident:
+                            # the solver stays resident for the next request
+                            # of its level
+                            r.slot.t_idle = t_done
+                            self.idle[r.level].append(r.slot)
+                        else:
+                            grave.append(r.slot)
                         n_active -= 1
                         progressed = True
                         n_retired += 1
@@ -387,7 +464,7 @@ class Server:
                     if st == TS_SOLVE_READY:
                         ready.append(r)
                     else:
-                        inflight += 8.0 ** (r.level - 7)
+                        inflight += r.work
                 active[lvl] = still
             batch = []
             yl = self.yield_level
@@ -398,10 +475,10 @@ class Server:
             for r in ready:  # already in priority order
                 if small and r.level > yl:
                     break
-                w = 8.0 ** (r.level - 7)
+                w = r.work
                 if inflight > 0.0 and inflight + w > self.inflight_work:
                     break
-                batch.append(r.sv)
+                batch.append(r.slot.sv)
                 inflight += w
             if batch:
                 try:
@@ -429,7 +506,7 @@ class Server:
         summ = summarize(reqs, t_end, occ_area, ledger.peak, peak_dev)
         summ["mean_active_by_level"] = {int(l): round(a / max(t_end, 1e-9), 2)
                                         for l, a in sorted(occ_level.items())}
-        summ["mean_admitted_gb"] = round(used_area / max(t_end, 1e-9) / 2 ** 30, 3)
+        summ["mean_held_gb"] = round(used_area / max(t_end, 1e-9) / 2 ** 30, 3)
         if dev_samples:
             b = np.array([d for _, d in dev_samples], dtype=np.float64)
             summ["library_gb_over_time"] = {"samples": len(dev_samples),
@@ -440,11 +517,17 @@ class Server:
                                  "mean": round(float(np.mean(ledger.release_s)), 3),
                                  "max": round(float(np.max(ledger.release_s)), 3)}
         summ["levels_shared"] = self.shared
+        summ["resident_reused"] = self.reused
+        summ["resident_evicted"] = self.evicted
+        summ["resident_idle_at_end"] = sum(len(v) for v in self.idle.values())
         return reqs, summ
 
     def close(self):
         self.pool.shutdown(wait=True)
         self.reaper.shutdown(wait=True)
+        for lst in self.idle.values():
+            self._destroy_now(lst)
+        self.idle.clear()
         self.template = None
         self.built = set()
         if self.torch.cuda.is_available():
@@ -481,7 +564,7 @@ def summarize(reqs, t_end, occ_area, peak_used, peak_dev):
         "mean_queue_ms": round(float(np.mean([r.t_admit - r.t for r in ok])) * 1e3, 2)
         if ok else None,
         "mean_active": round(occ_area / max(t_end, 1e-9), 2),
-        "peak_admitted_gb": round(peak_used / 2 ** 30, 3),
+        "peak_held_gb": round(peak_used / 2 ** 30, 3),
         "peak_library_gb": round(peak_dev / 2 ** 30, 3),
         "max_rel_residual": float(max(r.rel for r in ok)) if ok else None,
         "wall_s": round(t_end, 3),
@@ -503,6 +586,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--yield-level", type=int, default=None,
                     help="hold higher levels while requests up to this level are in flight")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="build and release a solver per request")
     args = ap.parse_args()
     from . import TS_F16W
     lo, hi = (int(v) for v in args.levels.split("-"))
@@ -511,7 +596,7 @@ def main():
                                  levels=tuple(range(lo, hi + 1)))
     srv = Server(topology=args.topology, precision=prec, rtol=args.rtol,
                  max_active=args.max_active, inflight_work=args.inflight_work,
-                 yield_level=args.yield_level,
+                 yield_level=args.yield_level, resident=not args.no_resident,
                  warm_levels=tuple(range(lo, hi + 1)))
     try:
         _, summ = srv.run(trace, log=lambda m: print(m, file=sys.stderr, flush=True))

@@ -144,6 +144,83 @@ def test_mesh_with_new_vertices_matches_a_fresh_mesh(ts):
         del ob
 
 
+@pytest.mark.parametrize("topo,kw,prec", [
+    ("shell288", {"method": 1, "q": 2, "fallback_tol": 0.25}, 1),
+    ("shell288", {"method": 1, "q": 2, "face_surrogate": True}, 0),
+    ("shell36", {"method": 1, "q": 2, "fallback_tol": 0.25}, 1),
+    ("shell288", {"method": 0}, 1),
+])
+def test_solver_with_new_vertices_matches_a_fresh_solver(ts, topo, kw, prec):
+    # a resident solver moved to another shell (ts_solver_set_vertices: mesh,
+    # fits, fallback flags, face fits, stored rows, coarse inverse rebuilt in
+    # place) gives bitwise what a solver built afresh on that shell gives
+    lam = 5
+    shell = getattr(inputs, topo)
+    va, t = shell(0.5, 1.0)
+    vb, _ = shell(0.62, 1.0)
+    kw = dict(kw, method={0: ts.TS_IFEM, 1: ts.TS_LSQP}[kw["method"]])
+    A = ts.Mesh(va, t)
+    oa = ts.Operator(A, lam, **kw)
+    sa = ts.Solver(oa, lam, rtol=1e-9, precision=prec)
+    fa = A.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(2, 0.5))
+    _, rc, _ = sa.solve(fa)
+    assert rc == ts.TS_OK
+    sa.set_vertices(vb)
+    B = ts.Mesh(vb, t)
+    ob = ts.Operator(B, lam, **kw)
+    sb = ts.Solver(ob, lam, rtol=1e-9, precision=prec)
+    if kw["method"] != ts.TS_IFEM:
+        for l in range(3, lam + 1):
+            assert np.array_equal(oa.coeffs(l), ob.coeffs(l))
+            assert np.array_equal(oa.macro_flags(l), ob.macro_flags(l))
+    x = B.to_block(lam, inputs.uniform(B.layout(lam).n_unique, 2))
+    assert torch.equal(oa.apply(lam, x), ob.apply(lam, x))
+    f = B.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(3, 0.62))
+    assert torch.equal(A.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(3, 0.62)), f)
+    ub, rcb, ib = sb.solve(f)
+    ua, rca, ia = sa.solve(f)
+    assert rca == rcb == ts.TS_OK and ia.cycles == ib.cycles
+    assert ia.rel_residual == ib.rel_residual and torch.equal(ua, ub)
+
+
+def test_solver_set_vertices_refusals(ts):
+    lam = 4
+    va, t = inputs.shell288(0.5, 1.0)
+    vb, _ = inputs.shell288(0.6, 1.0)
+    A = ts.Mesh(va, t)
+    op = ts.Operator(A, lam, method=ts.TS_LSQP, q=2)
+    sv = ts.Solver(op, lam, rtol=1e-8, precision=ts.TS_F32)
+    f = A.rhs(lam, ts.TS_RHS_BUMPS, inputs.gaussian_bumps(1, 0.5))
+    u0, rc, _ = sv.solve(f)
+    c0 = op.coeffs(4)
+    # a second operator on the mesh
+    other = ts.Operator(A, lam, method=ts.TS_IFEM)
+    with pytest.raises(ts.TSError) as e:
+        sv.set_vertices(vb)
+    assert e.value.code == ts.TS_EINVAL
+    del other
+    # a solve in progress
+    u = A.zeros(lam)
+    sv.begin(f, u)
+    with pytest.raises(ts.TSError) as e:
+        sv.set_vertices(vb)
+    assert e.value.code == ts.TS_EINVAL
+    while sv.query() != ts.TS_SOLVE_DONE:
+        if sv.query() == ts.TS_SOLVE_READY:
+            sv.step()
+    torch.cuda.synchronize()
+    assert torch.equal(u, u0)
+    # non-finite coordinates: refused, nothing changed
+    bad = vb.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(ts.TSError) as e:
+        sv.set_vertices(bad)
+    assert e.value.code == ts.TS_ENONFINITE
+    assert np.array_equal(op.coeffs(4), c0)
+    u1, rc1, _ = sv.solve(f)
+    assert rc1 == ts.TS_OK and torch.equal(u1, u0)
+
+
 def _trace(n, rate, levels, seed=3):
     return inputs.serving_trace(n, rate=rate, seed=seed, levels=levels)
 
@@ -161,6 +238,8 @@ def test_served_alone_and_in_mix_are_bitwise_equal(ts):
     mix = Server(max_active=24, keep=keep)
     rm, sm = mix.run(trace)
     mix.close()
+    bad = [(r.id, r.status, r.error) for r in ra + rm if r.status != ts.TS_OK]
+    assert not bad, bad
     assert sa["completed_ok"] == len(keep) and sm["completed_ok"] == len(trace)
     assert sm["mean_active"] > 2.0  # the mix really overlapped
     A = {r.id: r for r in ra}

@@ -12,12 +12,13 @@ algorithmic bytes per interior node, x read once and y written once; traffic
 from the committed rocprofv3 counter record of the same kernel source), the
 IFEM apply on the same GPU, q = 4, FP32 and FP16-weight applies, the residual,
 Gauss-Seidel sweeps, V(3,3) solves to 1e-10 in FP64 and with FP32 / FP16-weight
-cycles under FP64 refinement, a bounded run of the serve loop, and the CPU
+cycles under FP64 refinement, the single-macro latency and the 36-macro
+shell's apply, sweep and solves, a bounded run of the serve loop, and the CPU
 oracle timed on the free rows of the same operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--level 7] [--mesh shell288] [--only-volume] [--only-gs] [--no-solve] [--no-serve]
-       [--serve-requests 30]
+       [--no-small] [--serve-requests 30]
 """
 from __future__ import annotations
 
@@ -207,6 +208,79 @@ def solve_bench(ts, G, lam, op, log, keep=None):
     return out
 
 
+def small_configs(ts, log, stream):
+    """The two small workloads: one FP64 y = Ax on a single macro at level 5
+    (6,545 nodes; IFEM vs LSQP q = 2 latency), and the 36-macro shell at
+    level 6 (apply, Gauss-Seidel sweep, V(3,3) solves of the manufactured
+    problem to 1e-10 with the pure q = 2 surrogate, with the selective
+    surrogate that keeps IFEM rows on macros whose fit fails its check, and
+    with IFEM)."""
+    import torch
+
+    from paper_1608_06473_amd import inputs, study
+    out = {}
+    v, t = inputs.single_macro()
+    M = ts.Mesh(v, t)
+    lam = 5
+    info = M.layout(lam)
+    x = M.to_block(lam, inputs.uniform(info.n_unique, 0))
+    res = {"workload": "single macro of the shell r in [0.55, 1], level 5, %d nodes, FP64 y = Ax"
+                       % info.n_unique}
+    ys = {}
+    for name, kw in (("ifem", dict(method=ts.TS_IFEM)), ("lsqp_q2", dict(method=ts.TS_LSQP, q=2))):
+        op = ts.Operator(M, lam, sample_j=2, **kw)
+        y = M.zeros(lam)
+        ts.ts_apply(op.h, lam, ts.TS_F64, x, y, stream)
+        us = time_events(lambda: ts.ts_apply(op.h, lam, ts.TS_F64, x, y, stream), 50, stream) * 1e3
+        torch.cuda.synchronize()
+        ys[name] = y
+        res[name + "_us"] = round(us, 2)
+        del op
+    res["max_rel_diff"] = float((ys["lsqp_q2"] - ys["ifem"]).abs().max() / ys["ifem"].abs().max())
+    out["single_macro_l5"] = res
+    log("single macro level 5: IFEM %.1f us, LSQP q=2 %.1f us" % (res["ifem_us"], res["lsqp_q2_us"]))
+
+    v, t = inputs.shell36(study.R1, study.R2)
+    M = ts.Mesh(v, t)
+    lam = 6
+    info = M.layout(lam)
+    x = M.to_block(lam, inputs.uniform(info.n_unique, 0))
+    f = M.rhs(lam, ts.TS_RHS_MANUFACTURED, [study.R1, study.R2])
+    res = {"workload": "36-macro shell r in [0.55, 1], level 6, %d free DoF, q = 2, manufactured "
+                       "u = sin(pi (r - 0.55) / 0.45) x y z, FP64 V(3,3) to 1e-10" % info.n_free}
+    op = ts.Operator(M, lam, method=ts.TS_LSQP, q=2, sample_j=2)
+    y = M.zeros(lam)
+    ts.ts_apply(op.h, lam, ts.TS_F64, x, y, stream)
+    ms = time_events(lambda: ts.ts_apply(op.h, lam, ts.TS_F64, x, y, stream), 20, stream)
+    u = x.clone()
+    gs = time_events(lambda: ts.ts_smooth(op.h, lam, ts.TS_F64, f, u, 1, stream), 5, stream)
+    res["apply_ms"] = round(ms, 4)
+    res["apply_gdofs"] = round(info.n_free / ms / 1e6, 2)
+    res["gs_sweep_ms"] = round(gs, 4)
+    del op, y, u
+    for name, kw in (("lsqp_q2", dict(method=ts.TS_LSQP, q=2)),
+                     ("lsqp_q2_selective", dict(method=ts.TS_LSQP, q=2, fallback_tol=0.25)),
+                     ("ifem", dict(method=ts.TS_IFEM))):
+        op = ts.Operator(M, lam, sample_j=2, **kw)
+        sv = ts.Solver(op, lam, precision=ts.TS_F64, rtol=1e-10, max_cycles=100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, rc, si = sv.solve(f, raise_on_fail=False)
+        torch.cuda.synchronize()
+        r = {"status": int(rc), "cycles": int(si.cycles),
+             "ms": round((time.perf_counter() - t0) * 1e3, 1),
+             "rel_residual": float(si.rel_residual)}
+        if rc == ts.TS_OK:
+            r["error"] = study.error_norm(M, lam, u)
+        if kw.get("fallback_tol"):
+            r["ifem_macros_by_level"] = {l: int(op.macro_flags(l).sum()) for l in range(3, lam + 1)}
+        res[name] = r
+        log("36-macro shell level 6, %s: %s" % (name, json.dumps(r)))
+        del sv, op
+    out["shell36_l6"] = res
+    return out
+
+
 def serve_bench(n_requests, log):
     from paper_1608_06473_amd import inputs
     from paper_1608_06473_amd.serve import Server
@@ -239,6 +313,8 @@ def main():
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the single-macro and 36-macro workloads")
     ap.add_argument("--serve-requests", type=int, default=30)
     args = ap.parse_args()
 
@@ -418,6 +494,8 @@ def main():
     solutions = {} if not args.no_cpu else None
     if not args.no_solve:
         extra["solve"] = solve_bench(ts, G, lam, op, log, keep=solutions)
+    if not args.no_small:
+        extra["small_configs"] = small_configs(ts, log, stream)
     if not args.no_serve:
         extra["serving"] = serve_bench(args.serve_requests, log)
 

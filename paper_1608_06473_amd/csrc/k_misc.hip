@@ -749,19 +749,28 @@ __device__ __forceinline__ int basis_row(int q, int N, int i, int j, int k, doub
     return c;
 }
 
-// G = A^T A and its Cholesky factor (lower, row-major) into work[0..mq*mq)
-__global__ __launch_bounds__(256) void k_fit_gram(int N, int q, const int* __restrict__ pts, int npts,
-                                                  double* __restrict__ work) {
+// The least-squares matrix of a level's fit, A[p][c] = c-th basis function
+// at sampling point p (npts x mq); it depends on the level and the sampling
+// set only, not on the geometry
+__global__ __launch_bounds__(256) void k_fit_basis(int N, int q, const int* __restrict__ pts,
+                                                   int npts, double* __restrict__ Ab) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
+    double row[35];
+    basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
+    for (int c = 0; c < mq; c++) Ab[(size_t)p * mq + c] = row[c];
+}
+
+// G = A^T A and its Cholesky factor (lower, row-major) into Lf[0..mq*mq)
+__global__ __launch_bounds__(256) void k_fit_gram(int q, const double* __restrict__ Ab, int npts,
+                                                  double* __restrict__ Lf) {
     __shared__ double G[35 * 35];
     const int mq = (q + 1) * (q + 2) * (q + 3) / 6;
     for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) {
         const int a = e / mq, b = e % mq;
         double s = 0.0;
-        double row[35];
-        for (int p = 0; p < npts; p++) {
-            basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
-            s += row[a] * row[b];
-        }
+        for (int p = 0; p < npts; p++) s += Ab[(size_t)p * mq + a] * Ab[(size_t)p * mq + b];
         G[e] = s;
     }
     __syncthreads();
@@ -779,14 +788,15 @@ __global__ __launch_bounds__(256) void k_fit_gram(int N, int q, const int* __res
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) work[e] = G[e];
+    for (int e = threadIdx.x; e < mq * mq; e += blockDim.x) Lf[e] = G[e];
 }
 
 // per macro: rhs = A^T B_m, then (L L^T) a = rhs; then one step of
 // iterative refinement, rhs = A^T (B_m - A a) in FP64 and (L L^T) d = rhs,
 // a += d, so that the accuracy of a is no longer limited by the squared
-// condition number of the normal equations.  coef[m][w][c]
-__global__ __launch_bounds__(256) void k_fit_solve(int N, int q, const int* __restrict__ pts, int npts,
+// condition number of the normal equations.  coef[m][w][c].  Thread (c, w)
+// walks the sampling points in order.
+__global__ __launch_bounds__(256) void k_fit_solve(int q, const double* __restrict__ Ab, int npts,
                                                    const double* __restrict__ Bv, const double* __restrict__ Lf,
                                                    double* __restrict__ coef) {
     __shared__ double R[35 * NW];
@@ -798,12 +808,11 @@ __global__ __launch_bounds__(256) void k_fit_solve(int N, int q, const int* __re
         for (int e = threadIdx.x; e < mq * NW; e += blockDim.x) {
             const int c = e / NW, w = e % NW;
             double s = 0.0;
-            double row[35];
             for (int p = 0; p < npts; p++) {
-                const int nb = basis_row(q, N, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], row);
+                const double* row = Ab + (size_t)p * mq;
                 double b = Bm[(size_t)p * NW + w];
                 if (pass == 1)
-                    for (int c2 = 0; c2 < nb; c2++) b -= row[c2] * Z[c2 * NW + w];
+                    for (int c2 = 0; c2 < mq; c2++) b -= row[c2] * Z[c2 * NW + w];
                 s += row[c] * b;
             }
             R[c * NW + w] = s;
@@ -832,10 +841,16 @@ __global__ __launch_bounds__(256) void k_fit_solve(int N, int q, const int* __re
     }
 }
 
-void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt, double* coef,
-                double* work, hipStream_t s) {
-    k_fit_gram<<<1, 256, 0, s>>>(N, q, pts, npts, work);
-    k_fit_solve<<<nt, 256, 0, s>>>(N, q, pts, npts, B, work, coef);
+void launch_fit_basis(int N, int q, const int* pts, int npts, double* Ab, double* Lf,
+                      hipStream_t s) {
+    k_fit_basis<<<(npts + 255) / 256, 256, 0, s>>>(N, q, pts, npts, Ab);
+    k_fit_gram<<<1, 256, 0, s>>>(q, Ab, npts, Lf);
+    TS_HIP(hipGetLastError());
+}
+
+void launch_fit(int q, const double* Ab, int npts, const double* Lf, const double* B, int nt,
+                double* coef, hipStream_t s) {
+    k_fit_solve<<<nt, 256, 0, s>>>(q, Ab, npts, B, Lf, coef);
     TS_HIP(hipGetLastError());
 }
 
@@ -965,6 +980,7 @@ void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv,
     SBuf<double> c7((size_t)nt * 7 * mq, s), work((size_t)mq * mq, s);
     const std::vector<int> hpair(pair_of, pair_of + NW);
     SBuf<int> dpair(hpair, s), d2((size_t)6 * np, s);
+    SBuf<double> ab2((size_t)2 * np * mq, s);
     for (int p = 0; p < 7; p++) {
         std::vector<int> p2((size_t)6 * np);
         for (int h = 0; h < 2; h++) {
@@ -976,7 +992,8 @@ void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv,
             }
         }
         TS_HIP(hipMemcpyAsync(d2.p, p2.data(), p2.size() * sizeof(int), hipMemcpyHostToDevice, s));
-        k_fit_gram<<<1, 256, 0, s>>>(2 * N, q, d2.p, 2 * np, work.p);
+        k_fit_basis<<<(2 * np + 255) / 256, 256, 0, s>>>(2 * N, q, d2.p, 2 * np, ab2.p);
+        k_fit_gram<<<1, 256, 0, s>>>(q, ab2.p, 2 * np, work.p);
         k_fit_solve_pair<<<nt, 64, 0, s>>>(2 * N, q, d2.p, np, Bv, work.p, pw[p][0], pw[p][1],
                                           p, c7.p);
         TS_HIP(hipStreamSynchronize(s));  // p2, d2 and work are reused by the next pair
@@ -1019,31 +1036,36 @@ __global__ __launch_bounds__(64) void k_dense_assemble(const MacroGeom* __restri
 //   A[i,K] = -A[i,K] D (i outside K);  A[K,j] = P[:,j] (j outside K);  A[K,K] = D.
 constexpr int GJB = 64;
 
-// D = A[K,K]^-1 by unblocked Gauss-Jordan in LDS (one workgroup)
-__global__ __launch_bounds__(64) void k_bgj_diag(const double* __restrict__ A, int n, int k0,
-                                                 int b, double* __restrict__ D) {
-    // one wavefront; lane j owns column j of the block during the elimination
+// D = A[K,K]^-1 by unblocked Gauss-Jordan in LDS (one workgroup of four
+// wavefronts): thread (r, j) owns column j of rows r, r + 4, ...; per pivot
+// k the scaled pivot row and the old pivot column are published first, then
+// every entry is updated independently
+__global__ __launch_bounds__(256) void k_bgj_diag(const double* __restrict__ A, int n, int k0,
+                                                  int b, double* __restrict__ D) {
     __shared__ double M[GJB][GJB + 1];
     __shared__ double col[GJB];
-    const int j = (int)threadIdx.x;
-    for (int i = 0; i < b; i++) M[i][j] = j < b ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+    __shared__ double prow[GJB];
+    const int j = (int)threadIdx.x & 63, r0 = (int)threadIdx.x >> 6;
+    for (int i = r0; i < GJB; i += 4) M[i][j] = (i < b && j < b) ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
     __syncthreads();
     for (int k = 0; k < b; k++) {
-        const double piv = M[k][k];
-        if (j < b) col[j] = M[j][k];
+        if (r0 == 0 && j < b) {
+            const double piv = M[k][k];
+            col[j] = M[j][k];
+            prow[j] = (j == k) ? 1.0 / piv : M[k][j] / piv;
+        }
         __syncthreads();
         if (j < b) {
-            const double nk = (j == k) ? 1.0 / piv : M[k][j] / piv;
-            M[k][j] = nk;
-            // rows are independent: unrolled so that their LDS round trips
-            // overlap
-#pragma unroll 16
-            for (int i = 0; i < b; i++)
-                if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - col[i] * nk;
+            const double nk = prow[j];
+#pragma unroll
+            for (int q = 0; q < GJB / 4; q++) {
+                const int i = r0 + 4 * q;
+                if (i < b) M[i][j] = (i == k) ? nk : (j == k ? 0.0 : M[i][j]) - col[i] * nk;
+            }
         }
         __syncthreads();
     }
-    for (int e = j; e < b * b; e += 64) D[e] = M[e / b][e % b];
+    for (int e = (int)threadIdx.x; e < b * b; e += 256) D[e] = M[e / b][e % b];
 }
 
 // P[r][j] = sum_s D[r][s] A[k0+s][j] for every column j (b x n)
@@ -1133,7 +1155,7 @@ void launch_gj_blocked(double* A, int n, double* work, hipStream_t s) {
     const unsigned gt = (unsigned)((n + 63) / 64), gc = (unsigned)((n + 255) / 256);
     for (int k0 = 0; k0 < n; k0 += GJB) {
         const int b = std::min(GJB, n - k0);
-        k_bgj_diag<<<1, 64, 0, s>>>(A, n, k0, b, D);
+        k_bgj_diag<<<1, 256, 0, s>>>(A, n, k0, b, D);
         k_bgj_panel<<<dim3(gc, b), 256, 0, s>>>(A, n, k0, b, D, P);
         k_bgj_update<<<dim3(gt, gt), 256, 0, s>>>(A, n, k0, b, P);
         k_bgj_cols<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(A, n, k0, b, D);

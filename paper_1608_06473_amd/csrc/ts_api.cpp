@@ -145,14 +145,21 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
         const int np = (int)pts.size() / 3;
         TS_REQUIRE(np >= mq, TS_EINVAL, "sampling set smaller than the polynomial space");
-        SBuf<int> dp(pts, s);
-        SBuf<double> Bv((size_t)M.nt * np * NW, s), work((size_t)mq * mq, s);
+        if (!lo->fit_pts.p) {
+            lo->fit_pts.upload(pts);
+            if (op->p.method != TS_LSQP_SYM) {
+                lo->fit_basis.alloc((size_t)np * mq);
+                lo->fit_gram.alloc((size_t)mq * mq);
+                launch_fit_basis(N, q, lo->fit_pts.p, np, lo->fit_basis.p, lo->fit_gram.p, s);
+            }
+        }
+        SBuf<double> Bv((size_t)M.nt * np * NW, s);
         lo->coef64.alloc((size_t)M.nt * NW * mq);
-        launch_sample(M, lam, dp.p, np, Bv.p, s);
+        launch_sample(M, lam, lo->fit_pts.p, np, Bv.p, s);
         if (op->p.method == TS_LSQP_SYM)
             launch_fit_sym(N, q, pts, Bv.p, (int)M.nt, lo->coef64.p, s);
         else
-            launch_fit(N, q, dp.p, np, Bv.p, (int)M.nt, lo->coef64.p, work.p, s);
+            launch_fit(q, lo->fit_basis.p, np, lo->fit_gram.p, Bv.p, (int)M.nt, lo->coef64.p, s);
         std::vector<double> h((size_t)M.nt * NW * mq);
         TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         TS_HIP(hipStreamSynchronize(s));

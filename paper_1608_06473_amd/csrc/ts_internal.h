@@ -280,6 +280,10 @@ struct LevelOp {
     // the face, its face type); face_fit: used on this level
     DBuf<double> fcoef;
     bool face_fit = false;
+    // the fit's sampling points, least-squares matrix and Gram factor
+    // (geometry-independent: kept when the level is rebuilt for new vertices)
+    DBuf<int> fit_pts;
+    DBuf<double> fit_basis, fit_gram;
 };
 
 }  // namespace ts
@@ -352,8 +356,12 @@ void launch_cons_stencils(const Mesh& M, int lam, double* coef, hipStream_t s);
 // per-direction polynomials [nt][15][mq] (centre: minus the sum)
 void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* B, int nt,
                     double* coef15, hipStream_t s);
-void launch_fit(int N, int q, const int* pts, int npts, const double* B, int nt, double* coef,
-                double* work, hipStream_t s);
+// least-squares matrix of a level's fit (npts x mq) and the Cholesky factor
+// of its Gram matrix (mq x mq); they depend on the level and sampling set only
+void launch_fit_basis(int N, int q, const int* pts, int npts, double* Ab, double* Lf,
+                      hipStream_t s);
+void launch_fit(int q, const double* Ab, int npts, const double* Lf, const double* B, int nt,
+                double* coef, hipStream_t s);
 void launch_dense_assemble_cp(const Mesh& M, int lam, const int* off, const int4* cp, int nfree,
                               const int* slot_free, double* A, hipStream_t s);
 void launch_transpose(const double* a, double* b, int n, hipStream_t s);

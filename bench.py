@@ -33,6 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFS = 78.6   # MI355X FP64 vector
+# the paper's count for one IFEM update: 24 element matrices, edge sums and
+# the central weight (1,353 FLOP) plus the 29 FLOP of the application
+IFEM_FLOP_PER_NODE = 1353 + 29
 
 
 def log(*a):
@@ -310,6 +314,8 @@ def main():
                     help="time only the surrogate volume kernel (profiling runs)")
     ap.add_argument("--only-gs", action="store_true",
                     help="time only the FP64 Gauss-Seidel sweep (profiling runs)")
+    ap.add_argument("--only-ifem", action="store_true",
+                    help="time only the IFEM volume rows, FP64 apply (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-solve", action="store_true")
@@ -404,14 +410,31 @@ def main():
         return
 
     extra = {}
-    # IFEM apply (comparison path)
+    # IFEM apply (comparison path): whole operator, and its volume rows
+    # against the FP64 vector peak with the paper's count of 1,353 FLOP per
+    # stencil assembly plus 29 per application (Tab. flops)
     opI = ts.Operator(G, lam, method=ts.TS_IFEM)
     ts.ts_apply(opI.h, lam, ts.TS_F64, xb, yb, stream)
+    if args.only_ifem:
+        iv = time_events(lambda: ts.ts_apply_volume(opI.h, lam, ts.TS_F64, xb, yb, stream), 3,
+                         stream)
+        log("IFEM volume rows (FP64): %.3f ms" % iv)
+        return
     ifem_ms = time_events(lambda: ts.ts_apply(opI.h, lam, ts.TS_F64, xb, yb, stream), 3, stream)
+    ifem_vol = time_events(lambda: ts.ts_apply_volume(opI.h, lam, ts.TS_F64, xb, yb, stream), 3,
+                           stream)
+    ifem_tf = IFEM_FLOP_PER_NODE * info.n_volume / (ifem_vol / 1e3) / 1e12
     extra["ifem_apply"] = {"ms": round(ifem_ms, 4),
                            "gdofs": round(info.n_free / ifem_ms / 1e6, 3),
-                           "surrogate_speedup": round(ifem_ms / ms, 2)}
-    log("IFEM apply: %.3f ms (%.2f GDoF/s)" % (ifem_ms, info.n_free / ifem_ms / 1e6))
+                           "surrogate_speedup": round(ifem_ms / ms, 2),
+                           "volume_ms": round(ifem_vol, 4),
+                           "roofline": {"bound": "alu", "achieved": round(ifem_tf, 2),
+                                        "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                                        "frac": round(ifem_tf / FP64_PEAK_TFS, 4),
+                                        "flop_per_node": IFEM_FLOP_PER_NODE,
+                                        "kernel": "k_ifem_lds, FP64 apply, volume rows"}}
+    log("IFEM apply: %.3f ms (%.2f GDoF/s), volume rows %.3f ms (%.1f TFLOP/s)"
+        % (ifem_ms, info.n_free / ifem_ms / 1e6, ifem_vol, ifem_tf))
     del opI
     # q = 4 surrogate
     op4 = ts.Operator(G, lam, method=ts.TS_LSQP, q=4, sample_j=2)

@@ -193,18 +193,17 @@ class Server:
     max_active: slots; keep: ids whose solutions are copied to the host;
     inflight_work: budget of refinement iterations in flight, in units of a
     level-7 iteration on the 288-macro shell (request_work); one iteration is
-    always allowed;
-    warm_levels: levels whose layout data are built at start-up (else on the
-    first request that needs them); resident: keep the solver of a retired
-    request resident and serve the next request of its level with it (moved
-    to the new shell in place, ts_solver_set_vertices) instead of building
-    and releasing one per request; reserve_bytes: device memory that must
-    stay free beside an admitted request's estimate (the runtime needs some
-    for its own queues, and the estimate is only an estimate); yield_level:
-    while any request of this
-    level or below is being set up or solved, requests of higher levels get
-    no new iterations (their kernels would otherwise sit between the small
-    requests' many short kernels on the shared hardware queues); None: off.
+    always allowed; warm_levels: levels whose layout data are built at
+    start-up (else on the first request that needs them); resident: keep the
+    solver of a retired request resident and serve the next request of its
+    level with it (moved to the new shell in place, ts_solver_set_vertices)
+    instead of building and releasing one per request; reserve_bytes: device
+    memory that must stay free beside an admitted request's estimate (the
+    runtime needs some for its own queues, and the estimate is only an
+    estimate); yield_level: while any request of this level or below is being
+    set up or solved, requests of higher levels get no new iterations (their
+    kernels would otherwise sit between the small requests' many short
+    kernels on the shared hardware queues); None: off.
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,

@@ -328,6 +328,8 @@ class Server:
         active = collections.defaultdict(list)
         grave = []
         ledger = Ledger(self.hbm_budget, self.reserve_bytes)
+        # solvers left resident by an earlier run of this server hold memory
+        ledger.held = ledger.peak = sum(sl.bytes for lst in self.idle.values() for sl in lst)
         peak_dev = 0
         occ_area = 0.0
         occ_level = collections.defaultdict(float)  # time-weighted active count per level

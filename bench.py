@@ -19,7 +19,7 @@ oracle timed on the free rows of the same operator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--level 7] [--mesh shell288] [--only-volume] [--only-gs] [--no-solve] [--no-serve]
-       [--no-small] [--serve-requests 30]
+       [--no-small] [--serve-requests 30] [--serve-sustained 60]
 """
 from __future__ import annotations
 
@@ -286,19 +286,30 @@ def small_configs(ts, log, stream):
     return out
 
 
-def serve_bench(n_requests, log):
+def serve_bench(n_requests, log, sustained=60):
+    """The serve loop on the 288-macro topology: the first n_requests of the
+    Poisson(50/s) trace (a burst over the GPU's capacity: latency is
+    queueing), and `sustained` requests at 4/s, a rate one GPU keeps up with
+    (latency without a queue)."""
     from paper_1608_06473_amd import inputs
     from paper_1608_06473_amd.serve import Server
-    trace = inputs.serving_trace(n_requests, rate=50.0, seed=0)
-    srv = Server(topology="shell288", max_active=32, warm_levels=(4, 5, 6, 7))
-    reqs, summ = srv.run(trace)
-    srv.close()
-    summ["trace"] = ("first %d requests of the Poisson(50/s) trace, levels 4-7, r_in ~ U[0.4, 0.7], "
-                     "8 Gaussian bumps, FP32 V(3,3) + FP64 refinement to 1e-8, 288-macro shell "
-                     "topology; the layout's level data are built at server start-up, outside the "
-                     "latencies" % n_requests)
-    log("serving: %s" % json.dumps(summ))
-    return summ
+    out = {}
+    for key, n, rate in (("burst", n_requests, 50.0), ("sustained", sustained, 4.0)):
+        if n <= 0:
+            continue
+        trace = inputs.serving_trace(n, rate=rate, seed=0)
+        srv = Server(topology="shell288", max_active=32, warm_levels=(4, 5, 6, 7))
+        try:
+            _, summ = srv.run(trace)
+        finally:
+            srv.close()
+        summ["trace"] = ("first %d requests of the Poisson(%g/s) trace, levels 4-7, r_in ~ "
+                         "U[0.4, 0.7], 8 Gaussian bumps, FP32 V(3,3) + FP64 refinement to 1e-8, "
+                         "288-macro shell topology; the layout's level data are built at server "
+                         "start-up, outside the latencies" % (n, rate))
+        log("serving (%s): %s" % (key, json.dumps(summ)))
+        out[key] = summ
+    return out
 
 
 def main():
@@ -323,6 +334,8 @@ def main():
     ap.add_argument("--no-small", action="store_true",
                     help="skip the single-macro and 36-macro workloads")
     ap.add_argument("--serve-requests", type=int, default=30)
+    ap.add_argument("--serve-sustained", type=int, default=60,
+                    help="requests of the 4/s serving leg (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -527,7 +540,7 @@ def main():
     if not args.no_small:
         extra["small_configs"] = small_configs(ts, log, stream)
     if not args.no_serve:
-        extra["serving"] = serve_bench(args.serve_requests, log)
+        extra["serving"] = serve_bench(args.serve_requests, log, args.serve_sustained)
 
     cpu = None
     if not args.no_cpu:

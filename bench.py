@@ -448,7 +448,21 @@ def main():
                                         "kernel": "k_ifem_lds, FP64 apply, volume rows"}}
     log("IFEM apply: %.3f ms (%.2f GDoF/s), volume rows %.3f ms (%.1f TFLOP/s)"
         % (ifem_ms, info.n_free / ifem_ms / 1e6, ifem_vol, ifem_tf))
-    del opI
+    # one FP64 V(3,3) cycle with IFEM rows and with the q = 2 surrogate (the
+    # paper compares the two methods by their cycle times)
+    fI = G.rhs(lam, ts.TS_RHS_MANUFACTURED, [0.55, 1.0])
+    cyc = {}
+    for name, o in (("ifem", opI), ("lsqp_q2", op)):
+        svc = ts.Solver(o, lam, precision=ts.TS_F64, rtol=1e-10)
+        uI = G.zeros(lam)
+        ts.ts_vcycle(svc.h, ts.TS_F64, fI, uI, stream)
+        cyc[name] = time_events(lambda: ts.ts_vcycle(svc.h, ts.TS_F64, fI, uI, stream), 2, stream)
+        del svc, uI
+    extra["ifem_apply"]["vcycle_ms"] = round(cyc["ifem"], 2)
+    extra["ifem_apply"]["surrogate_vcycle_ms"] = round(cyc["lsqp_q2"], 2)
+    extra["ifem_apply"]["vcycle_ratio"] = round(cyc["ifem"] / cyc["lsqp_q2"], 2)
+    log("FP64 V(3,3) cycle: IFEM %.1f ms, LSQP q=2 %.1f ms" % (cyc["ifem"], cyc["lsqp_q2"]))
+    del opI, fI
     # q = 4 surrogate
     op4 = ts.Operator(G, lam, method=ts.TS_LSQP, q=4, sample_j=2)
     ts.ts_apply(op4.h, lam, ts.TS_F64, xb, yb, stream)

@@ -149,6 +149,8 @@ def test_mesh_with_new_vertices_matches_a_fresh_mesh(ts):
     ("shell288", {"method": 1, "q": 2, "face_surrogate": True}, 0),
     ("shell36", {"method": 1, "q": 2, "fallback_tol": 0.25}, 1),
     ("shell288", {"method": 0}, 1),
+    ("shell288", {"method": 2, "q": 2}, 0),
+    ("shell288", {"method": 3}, 1),
 ])
 def test_solver_with_new_vertices_matches_a_fresh_solver(ts, topo, kw, prec):
     # a resident solver moved to another shell (ts_solver_set_vertices: mesh,
@@ -158,7 +160,8 @@ def test_solver_with_new_vertices_matches_a_fresh_solver(ts, topo, kw, prec):
     shell = getattr(inputs, topo)
     va, t = shell(0.5, 1.0)
     vb, _ = shell(0.62, 1.0)
-    kw = dict(kw, method={0: ts.TS_IFEM, 1: ts.TS_LSQP}[kw["method"]])
+    kw = dict(kw, method={0: ts.TS_IFEM, 1: ts.TS_LSQP, 2: ts.TS_LSQP_SYM,
+                          3: ts.TS_CONS}[kw["method"]])
     A = ts.Mesh(va, t)
     oa = ts.Operator(A, lam, **kw)
     sa = ts.Solver(oa, lam, rtol=1e-9, precision=prec)
@@ -170,6 +173,7 @@ def test_solver_with_new_vertices_matches_a_fresh_solver(ts, topo, kw, prec):
     ob = ts.Operator(B, lam, **kw)
     sb = ts.Solver(ob, lam, rtol=1e-9, precision=prec)
     if kw["method"] != ts.TS_IFEM:
+        # every surrogate kind rebuilds its coefficients for the new shell
         for l in range(3, lam + 1):
             assert np.array_equal(oa.coeffs(l), ob.coeffs(l))
             assert np.array_equal(oa.macro_flags(l), ob.macro_flags(l))

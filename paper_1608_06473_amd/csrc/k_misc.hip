@@ -725,6 +725,27 @@ void launch_fallback_check(const Mesh& M, int lam, int q, const double* coef, do
     TS_HIP(hipGetLastError());
 }
 
+// FP32 and FP16-weight (pre-scaled by N) copies of a level's coefficients;
+// bad[0] is set when a coefficient is not finite
+__global__ __launch_bounds__(256) void k_coef_variants(const double* __restrict__ c, int64_t n,
+                                                       int N, float* __restrict__ c32,
+                                                       float* __restrict__ c16s,
+                                                       int* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = c[i];
+    c32[i] = (float)v;
+    c16s[i] = (float)(v * N);
+    if (!isfinite(v)) bad[0] = 1;
+}
+
+void launch_coef_variants(const double* c, int64_t n, int N, float* c32, float* c16s, int* bad,
+                          hipStream_t s) {
+    if (n == 0) return;
+    k_coef_variants<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(c, n, N, c32, c16s, bad);
+    TS_HIP(hipGetLastError());
+}
+
 void launch_sample(const Mesh& M, int lam, const int* pts, int npts, double* B, hipStream_t s) {
     const dim3 g((npts + 127) / 128, (unsigned)M.nt);
     k_sample<<<g, 128, 0, s>>>(B, M.d_geom.p, pts, npts, 1 << lam);

@@ -91,18 +91,6 @@ static void split_macros(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
     lo.face_fit = lo.fcoef.p && lo.n_ifem == 0;
 }
 
-// Surrogate rows of the level's interior faces, fitted to the exact face rows
-// (built here on s if they do not exist yet).
-static void setup_face_fit(ts_op* op, LevelOp& lo, int lam, hipStream_t s) {
-    Mesh& M = op->mesh->m;
-    const Level& L = M.level(lam);
-    const double* f2sten = face_stencils(M, lam, s);
-    const int m2 = (op->p.q + 1) * (op->p.q + 2) / 2;
-    lo.fcoef.alloc((size_t)M.nt * 4 * NW * m2);
-    launch_face_fit(L, f2sten, op->p.q, op->p.sample_j, (int)M.nt, lo.fcoef.p, s);
-    TS_HIP(hipStreamSynchronize(s));
-}
-
 static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vector<double>& h) {
     const int N = 1 << lam;
     std::vector<float> f32(h.size()), f16s(h.size());
@@ -115,9 +103,11 @@ static void upload_coef_variants(ts_op* op, LevelOp& lo, int lam, const std::vec
     lo.has_coef = true;
 }
 
-// Builds the level's geometry-dependent operator data; a level built before
-// (new vertex coordinates) is rebuilt in the buffers it has.
-static void setup_level(ts_op* op, int lam, hipStream_t s) {
+// Enqueues on s the level's geometry-dependent operator data (fits or
+// constant stencils, their FP32 / FP16-weight copies, face fits, the
+// fallback check); a level built before (new vertex coordinates) is rebuilt
+// in the buffers it has.  finish_levels reads the checks back.
+static void enqueue_level(ts_op* op, int lam, hipStream_t s) {
     Mesh& M = op->mesh->m;
     std::unique_ptr<LevelOp> lo;
     auto it = op->lv.find(lam);
@@ -128,19 +118,16 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
         lo = std::make_unique<LevelOp>();
     }
     lo->lam = lam;
+    lo->has_coef = false;
     M.level(lam);
-    if (op->p.method == TS_CONS && lam >= 3) {
+    const bool cons = op->p.method == TS_CONS && lam >= 3;
+    const bool sur = op->p.method != TS_IFEM && op->p.method != TS_CONS && lam >= 3;
+    if (cons) {
         // one stencil per macro: the exact stencil of its unmapped fine
         // tetrahedra, the same at every interior node (degree-0 coefficients)
         lo->coef64.alloc((size_t)M.nt * NW);
         launch_cons_stencils(M, lam, lo->coef64.p, s);
-        std::vector<double> h((size_t)M.nt * NW);
-        TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        TS_HIP(hipStreamSynchronize(s));
-        for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite constant stencil");
-        upload_coef_variants(op, *lo, lam, h);
-        split_macros(op, *lo, lam, s);
-    } else if (op->p.method != TS_IFEM && lam >= 3) {
+    } else if (sur) {
         const int N = 1 << lam, q = op->p.q, mq = op->mq;
         std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
         const int np = (int)pts.size() / 3;
@@ -160,15 +147,68 @@ static void setup_level(ts_op* op, int lam, hipStream_t s) {
             launch_fit_sym(N, q, pts, Bv.p, (int)M.nt, lo->coef64.p, s);
         else
             launch_fit(q, lo->fit_basis.p, np, lo->fit_gram.p, Bv.p, (int)M.nt, lo->coef64.p, s);
-        std::vector<double> h((size_t)M.nt * NW * mq);
-        TS_HIP(hipMemcpyAsync(h.data(), lo->coef64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        TS_HIP(hipStreamSynchronize(s));
-        for (double v : h) TS_REQUIRE(std::isfinite(v), TS_ENONFINITE, "non-finite surrogate coefficient");
-        upload_coef_variants(op, *lo, lam, h);
-        if (op->p.face_surrogate) setup_face_fit(op, *lo, lam, s);
-        split_macros(op, *lo, lam, s);
+    }
+    if (cons || sur) {
+        const size_t n = lo->coef64.n;
+        lo->coef32.alloc(n);
+        lo->coef16s.alloc(n);
+        lo->d_bad.alloc(1);
+        TS_HIP(hipMemsetAsync(lo->d_bad.p, 0, sizeof(int), s));
+        launch_coef_variants(lo->coef64.p, (int64_t)n, 1 << lam, lo->coef32.p, lo->coef16s.p,
+                             lo->d_bad.p, s);
+        if (sur && op->p.face_surrogate) {
+            const double* f2sten = face_stencils(M, lam, s);
+            const int m2 = (op->p.q + 1) * (op->p.q + 2) / 2;
+            lo->fcoef.alloc((size_t)M.nt * 4 * NW * m2);
+            launch_face_fit(M.level(lam), f2sten, op->p.q, op->p.sample_j, (int)M.nt,
+                            lo->fcoef.p, s);
+        }
+        if (op->p.fallback_tol > 0) {
+            lo->d_flags.alloc((size_t)M.nt);
+            launch_fallback_check(M, lam, op->p.q, lo->coef64.p, op->p.fallback_tol,
+                                  lo->d_flags.p, s);
+        }
     }
     op->lv[lam] = std::move(lo);
+}
+
+// One read-back for all levels: the non-finite flags (TS_ENONFINITE) and the
+// fallback flags, from which the surrogate and IFEM macro lists are built.
+static void finish_levels(ts_op* op, hipStream_t s) {
+    const int nt = (int)op->mesh->m.nt;
+    std::vector<LevelOp*> los;
+    for (auto& kv : op->lv)
+        if (kv.second->d_bad.p) los.push_back(kv.second.get());
+    std::vector<int> bad(los.size(), 0);
+    std::vector<std::vector<unsigned char>> fl(los.size());
+    for (size_t a = 0; a < los.size(); a++) {
+        TS_HIP(hipMemcpyAsync(&bad[a], los[a]->d_bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        fl[a].assign(nt, 0);
+        if (op->p.fallback_tol > 0)
+            TS_HIP(hipMemcpyAsync(fl[a].data(), los[a]->d_flags.p, nt, hipMemcpyDeviceToHost, s));
+    }
+    TS_HIP(hipStreamSynchronize(s));
+    for (size_t a = 0; a < los.size(); a++) {
+        LevelOp& lo = *los[a];
+        TS_REQUIRE(!bad[a], TS_ENONFINITE,
+                   op->p.method == TS_CONS ? "non-finite constant stencil"
+                                           : "non-finite surrogate coefficient");
+        lo.flags.swap(fl[a]);
+        std::vector<int> sur, ifem;
+        for (int t = 0; t < nt; t++) (lo.flags[t] ? ifem : sur).push_back(t);
+        lo.n_sur = (int)sur.size();
+        lo.n_ifem = (int)ifem.size();
+        if (lo.n_sur) lo.sur_list.upload(sur); else lo.sur_list.reset();
+        if (lo.n_ifem) lo.ifem_list.upload(ifem); else lo.ifem_list.reset();
+        lo.face_fit = lo.fcoef.p && lo.n_ifem == 0;
+        lo.has_coef = true;
+    }
+}
+
+// every level of the operator, built (or rebuilt) on s; synchronous
+static void setup_levels(ts_op* op, hipStream_t s) {
+    for (int lam = 2; lam <= op->max_level; lam++) enqueue_level(op, lam, s);
+    finish_levels(op, s);
 }
 
 // Interface Gauss-Seidel values of one phase (sized for the largest phase),
@@ -252,6 +292,10 @@ struct ts_solver {
     DBuf<double> AinvT, cwork;
     DBuf<int> c_off;
     DBuf<int64_t> c_slot;
+    // copies of the coarse free nodes and the free index of every block slot
+    // (connectivity only: built once, kept when the vertices change)
+    DBuf<int4> c_cp;
+    DBuf<int> c_sf;
     // outer iteration
     DBuf<double> r_outer;
     DBuf<float> r_in, e_in;
@@ -309,57 +353,54 @@ static void coarse_setup(ts_solver* sv, hipStream_t s) {
     const int lam = 2;
     Level& L = M.level(lam);
     const int N = L.N;
-    // free nodes: free lower-primitive nodes (canonical order), then the one
-    // interior node of every macro
-    std::vector<int> off_if;
-    std::vector<int4> cp_if;
-    std::vector<unsigned char> flag;
-    {
-        std::vector<int> o(L.n_if + 1);
-        std::vector<int4> c(L.if_copy.n);
-        flag.resize(L.n_if);
-        TS_HIP(hipMemcpy(o.data(), L.if_off.p, o.size() * sizeof(int), hipMemcpyDeviceToHost));
-        TS_HIP(hipMemcpy(c.data(), L.if_copy.p, c.size() * sizeof(int4), hipMemcpyDeviceToHost));
+    if (!sv->c_cp.p) {
+        // free nodes: free lower-primitive nodes (canonical order), then the
+        // one interior node of every macro
+        std::vector<int> off_if(L.n_if + 1);
+        std::vector<int4> cp_if(L.if_copy.n);
+        std::vector<unsigned char> flag(L.n_if);
+        TS_HIP(hipMemcpy(off_if.data(), L.if_off.p, off_if.size() * sizeof(int), hipMemcpyDeviceToHost));
+        TS_HIP(hipMemcpy(cp_if.data(), L.if_copy.p, cp_if.size() * sizeof(int4), hipMemcpyDeviceToHost));
         TS_HIP(hipMemcpy(flag.data(), L.if_flag.p, flag.size(), hipMemcpyDeviceToHost));
-        off_if = o;
-        cp_if = c;
+        std::vector<int> off{0};
+        std::vector<int4> cp;
+        std::vector<int64_t> slot;
+        std::vector<int> slot_free(L.len, -1);
+        int n = 0;
+        auto add_copy = [&](int4 q) {
+            cp.push_back(q);
+            const int64_t sl = (int64_t)q.x * L.B + bidx(N, q.y, q.z, q.w);
+            slot.push_back(sl);
+            slot_free[sl] = n;
+        };
+        for (int64_t t = 0; t < L.n_if; t++) {
+            if (flag[t] & 1) continue;
+            for (int c = off_if[t]; c < off_if[t + 1]; c++) add_copy(cp_if[c]);
+            n++;
+            off.push_back((int)cp.size());
+        }
+        for (int64_t m = 0; m < M.nt; m++) {
+            add_copy(make_int4((int)m, 1, 1, 1));
+            n++;
+            off.push_back((int)cp.size());
+        }
+        sv->n0 = n;
+        sv->c_off.upload(off);
+        sv->c_slot.upload(slot);
+        sv->c_sf.upload(slot_free);
+        sv->c_cp.upload(cp);
     }
-    std::vector<int> off{0};
-    std::vector<int4> cp;
-    std::vector<int64_t> slot;
-    std::vector<int> slot_free(L.len, -1);
-    int n = 0;
-    auto add_copy = [&](int4 q) {
-        cp.push_back(q);
-        const int64_t sl = (int64_t)q.x * L.B + bidx(N, q.y, q.z, q.w);
-        slot.push_back(sl);
-        slot_free[sl] = n;
-    };
-    for (int64_t t = 0; t < L.n_if; t++) {
-        if (flag[t] & 1) continue;
-        for (int c = off_if[t]; c < off_if[t + 1]; c++) add_copy(cp_if[c]);
-        n++;
-        off.push_back((int)cp.size());
-    }
-    for (int64_t m = 0; m < M.nt; m++) {
-        add_copy(make_int4((int)m, 1, 1, 1));
-        n++;
-        off.push_back((int)cp.size());
-    }
-    sv->n0 = n;
-    SBuf<int> d_off(off, s), d_sf(slot_free, s);
-    SBuf<int4> d_cp(cp, s);
-    sv->c_off.upload(off);
-    sv->c_slot.upload(slot);
+    // the IFEM matrix of the free coarse nodes for the current geometry and
+    // its inverse; the temporaries are released in the order of s
+    const int n = sv->n0;
     SBuf<double> A((size_t)n * n, s), work((size_t)64 * (n + 64), s);
     TS_HIP(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), s));
-    launch_dense_assemble_cp(M, lam, d_off.p, d_cp.p, n, d_sf.p, A.p, s);
+    launch_dense_assemble_cp(M, lam, sv->c_off.p, sv->c_cp.p, n, sv->c_sf.p, A.p, s);
     launch_gj_blocked(A.p, n, work.p, s);
     TS_HIP(hipGetLastError());
     sv->AinvT.alloc((size_t)n * n);
     launch_transpose(A.p, sv->AinvT.p, n, s);
     sv->cwork.alloc((2 + 4 * 16) * (size_t)n);  // fb, ub and the matvec partial sums
-    TS_HIP(hipStreamSynchronize(s));
 }
 
 template <class X>
@@ -597,7 +638,7 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             op->max_level = max_level;
             if (p->method == TS_CONS) op->p.q = 0;  // degree-0 "polynomials"
             op->mq = p->method == TS_IFEM ? 0 : mq_of(op->p.q);
-            for (int lam = 2; lam <= max_level; lam++) setup_level(op, lam, S(s));
+            setup_levels(op, S(s));
             TS_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
             TS_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
             TS_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
@@ -844,7 +885,7 @@ int ts_solver_set_vertices(ts_solver* sv, const double* vtx, ts_stream s) {
         }
         M.geo_gen++;  // stored coordinates and interface rows are rebuilt on use
         sv->state = 0;
-        for (int lam = 2; lam <= op->max_level; lam++) setup_level(op, lam, S(s));
+        setup_levels(op, S(s));
         check_exact_rows(op, sv->L, sv->p.dd);
         solver_geometry(sv, S(s));
     });

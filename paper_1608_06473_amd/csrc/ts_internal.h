@@ -284,6 +284,10 @@ struct LevelOp {
     // (geometry-independent: kept when the level is rebuilt for new vertices)
     DBuf<int> fit_pts;
     DBuf<double> fit_basis, fit_gram;
+    // set-up results read back once for all levels: the fallback check's
+    // per-macro flags and the non-finite-coefficient flag
+    DBuf<unsigned char> d_flags;
+    DBuf<int> d_bad;
 };
 
 }  // namespace ts
@@ -331,6 +335,8 @@ void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const 
 void launch_ifem_volume(const ts_op* op, int lam, int dtype, int mode, const void* x, void* y,
                         const void* f, int colour, hipStream_t s, const int* mlist = nullptr,
                         int n_list = -1);
+void launch_coef_variants(const double* c, int64_t n, int N, float* c32, float* c16s, int* bad,
+                          hipStream_t s);
 void launch_fallback_check(const Mesh& M, int lam, int q, const double* coef, double tol,
                            unsigned char* flags, hipStream_t s);
 void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* rc, hipStream_t s);

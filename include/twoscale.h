@@ -157,7 +157,8 @@ const char *ts_last_error(void);
  * rho the barycentric blend of the vertex radii (nodes of interior macros
  * form spherical layers); TS_GEOM_AFFINE keeps x = y (Phi = Id).  Fails with
  * TS_EINVAL if a face is shared by more than two macros, an id is out of
- * range or a macro is degenerate. */
+ * range or a macro is degenerate (the volume spanned by its edges from
+ * vertex 0 at most 1e-12 times the cube of the longest of them). */
 int ts_mesh_create(const double *vtx, int64_t nv, const int64_t *tet, int64_t nt, int geom,
                    ts_mesh **out);
 int ts_mesh_destroy(ts_mesh *mesh);

@@ -144,7 +144,13 @@ void build_geometry(Mesh& M) {
         }
         double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
                      e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
-        TS_REQUIRE(fabs(det) > 1e-300, TS_EINVAL, "degenerate macro tetrahedron");
+        // relative to the cube of its longest edge from vertex 0: flat (or
+        // nearly flat) macros are refused
+        double l2 = 0.0;
+        for (const double* e : {e1, e2, e3})
+            l2 = std::max(l2, e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        TS_REQUIRE(std::isfinite(det) && fabs(det) > 1e-12 * l2 * sqrt(l2), TS_EINVAL,
+                   "degenerate macro tetrahedron");
     }
     M.geomh.swap(gh);
     if (M.d_geom.p && M.d_geom.n == M.geomh.size())

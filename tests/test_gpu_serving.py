@@ -274,3 +274,19 @@ def test_served_solution_residual_by_oracle(ts):
     ucan[ids] = u
     res = O.residual(N, f, ucan, kind=oracle.LSQP, q=2, coeffs=c, flags=fl)
     assert O.norm_free(N, res) / O.norm_free(N, f) <= 1.05e-8
+
+
+def test_failed_setup_ends_its_request_only(ts):
+    # a request whose shell is invalid (inner radius above the outer one:
+    # the mesh check refuses it) fails alone; the requests around it, on
+    # new and on resident solvers, are served
+    from paper_1608_06473_amd.serve import Server
+    trace = _trace(8, 200.0, (4,), seed=11)
+    trace[3] = dict(trace[3], r_in=1.2)
+    srv = Server(max_active=3)
+    reqs, summ = srv.run(trace)
+    srv.close()
+    by = {r.id: r for r in reqs}
+    assert by[trace[3]["id"]].status == ts.TS_EINVAL
+    assert all(by[rec["id"]].status == ts.TS_OK for i, rec in enumerate(trace) if i != 3)
+    assert summ["failed"] == 1 and summ["completed_ok"] == 7

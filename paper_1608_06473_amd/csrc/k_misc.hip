@@ -881,9 +881,9 @@ void launch_fit(int q, const double* Ab, int npts, const double* Lf, const doubl
 // of the level with 2N intervals, so the pair's points are given in doubled
 // coordinates and the ordinary basis rows of that level apply.  Right-hand
 // side of pair p: the first np points carry the weight of w at the samples,
-// the next np that of wo; Lf is the Cholesky factor of the pair's Gram
-// matrix.  coef7[m][p][c].
-__global__ __launch_bounds__(64) void k_fit_solve_pair(int N2, int q, const int* __restrict__ pts2,
+// the next np that of wo; Ab holds the basis rows of the 2 np points and Lf
+// the Cholesky factor of their Gram matrix.  coef7[m][p][c].
+__global__ __launch_bounds__(64) void k_fit_solve_pair(int q, const double* __restrict__ Ab,
                                                        int np, const double* __restrict__ Bv,
                                                        const double* __restrict__ Lf, int w,
                                                        int wo, int p,
@@ -898,12 +898,11 @@ __global__ __launch_bounds__(64) void k_fit_solve_pair(int N2, int q, const int*
     for (int pass = 0; pass < 2; pass++) {
         for (int c = threadIdx.x; c < mq; c += blockDim.x) {
             double sum = 0.0;
-            double row[35];
             for (int t = 0; t < 2 * np; t++) {
-                const int nb = basis_row(q, N2, pts2[3 * t], pts2[3 * t + 1], pts2[3 * t + 2], row);
+                const double* row = Ab + (size_t)t * mq;
                 double b = Bm[(size_t)(t < np ? t : t - np) * NW + (t < np ? w : wo)];
                 if (pass == 1)
-                    for (int c2 = 0; c2 < nb; c2++) b -= row[c2] * Z[c2];
+                    for (int c2 = 0; c2 < mq; c2++) b -= row[c2] * Z[c2];
                 sum += row[c] * b;
             }
             R[c] = sum;
@@ -1015,8 +1014,8 @@ void launch_fit_sym(int N, int q, const std::vector<int>& pts, const double* Bv,
         TS_HIP(hipMemcpyAsync(d2.p, p2.data(), p2.size() * sizeof(int), hipMemcpyHostToDevice, s));
         k_fit_basis<<<(2 * np + 255) / 256, 256, 0, s>>>(2 * N, q, d2.p, 2 * np, ab2.p);
         k_fit_gram<<<1, 256, 0, s>>>(q, ab2.p, 2 * np, work.p);
-        k_fit_solve_pair<<<nt, 64, 0, s>>>(2 * N, q, d2.p, np, Bv, work.p, pw[p][0], pw[p][1],
-                                          p, c7.p);
+        k_fit_solve_pair<<<nt, 64, 0, s>>>(q, ab2.p, np, Bv, work.p, pw[p][0], pw[p][1], p,
+                                          c7.p);
         TS_HIP(hipStreamSynchronize(s));  // p2, d2 and work are reused by the next pair
     }
     k_sym_shift<<<(nt * 14 + 63) / 64, 64, 0, s>>>(c7.p, dpair.p, nt, q, N, coef15);

@@ -17,13 +17,14 @@ namespace ts {
 // element-wise partial stencil of each adjacent macro), the partial sums are
 // reduced across the wavefront in a fixed tree order, and the lanes write the
 // copies.  MODE 0: y = L x; 1: y = f - L x, written to every copy; 2:
-// Gauss-Seidel value (f - off) / diag into tmp[t].
+// Gauss-Seidel value (f - off) / diag, written to every copy for t <
+// n_direct, else into tmp[t - n_direct].
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_iface(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
     const int* __restrict__ off, const int4* __restrict__ cp, const int* __restrict__ rc_base,
     const double* __restrict__ sten, int n_rc, const int* __restrict__ list, int n, int N,
-    int64_t B, double* __restrict__ tmp) {
+    int64_t B, double* __restrict__ tmp, int n_direct) {
     const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
     if (t >= n) return;  // whole wavefront
@@ -51,7 +52,15 @@ __global__ __launch_bounds__(256) void k_iface(
     const int4 q0 = cp[c0];
     const size_t s0 = (size_t)q0.x * B + bidx(N, q0.y, q0.z, q0.w);
     if (MODE == 2) {
-        if (lane == 0) tmp[t] = ((double)f[s0] - of) / dg;
+        const double g = ((double)f[s0] - of) / dg;
+        if (t >= n_direct) {
+            if (lane == 0) tmp[t - n_direct] = g;
+            return;
+        }
+        for (int c = c0 + lane; c < c1; c += 64) {
+            const int4 q = cp[c];
+            y[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = (T)g;
+        }
         return;
     }
     double v = dg * (double)x[s0] + of;
@@ -89,10 +98,10 @@ __global__ __launch_bounds__(256) void k_face2(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
     const int4* __restrict__ cp, const double* __restrict__ sten,
     const double* __restrict__ fcoef, int n2, const int* __restrict__ list, int n, int N,
-    int64_t B, double* __restrict__ tmp) {
+    int64_t B, double* __restrict__ tmp, int n_direct) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    face2_node<T, MODE, FQ>(x, y, f, cp, sten, fcoef, n2, list, t, N, B, tmp);
+    face2_node<T, MODE, FQ>(x, y, f, cp, sten, fcoef, n2, list, t, N, B, tmp, n_direct);
 }
 
 // Least-squares fit of the face rows of one interior face per workgroup: the
@@ -461,11 +470,15 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     const int n2 = skip_face ? 0 : phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
-    double* tmp_r = tmp ? tmp + n2 : nullptr;
+    // Gauss-Seidel: the uncoupled nodes of the phase are written in place,
+    // the coupled ones go to tmp (face nodes first, then the general ones)
+    const int d2 = phase >= 0 ? L.n_f2_direct[phase] : 0;
+    const int dr = phase >= 0 ? L.n_rest_direct[phase] : 0;
+    double* tmp_r = tmp ? tmp + (n2 - d2) : nullptr;
 #define TS_F2Q(T_, M_, Q_)                                                                    \
     k_face2<T_, M_, Q_><<<(n2 + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,   \
                                                          cp2, sten, fc, L.n_f2, nullptr, n2,  \
-                                                         L.N, L.B, tmp)
+                                                         L.N, L.B, tmp, d2)
 #define TS_F2(T_, M_)                                                                         \
     do {                                                                                      \
         switch (fq) {                                                                         \
@@ -480,7 +493,7 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     k_iface<T_, M_><<<(nr + 3) / 4, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,           \
                                                      L.if_off.p, L.if_copy.p, L.rc_base.p,    \
                                                      G.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
-                                                     tmp_r)
+                                                     tmp_r, dr)
     if (n2) {
         if (dtype == TS_F64) {
             if (mode == 0) TS_F2(double, 0); else if (mode == 1) TS_F2(double, 1); else TS_F2(double, 2);
@@ -508,22 +521,27 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     TS_HIP(hipGetLastError());
 }
 
+// the coupled nodes of a phase (after the uncoupled ones in each list) take
+// their values from tmp once every node of the phase is computed
 void launch_iface_scatter(const ts_op* op, int lam, int dtype, int phase, const double* tmp,
                           void* u, hipStream_t s) {
     const Mesh& M = op->mesh->m;
     const Level& L = const_cast<Mesh&>(M).level(lam);
-    const int n2 = L.n_f2_phase[phase], nr = L.n_rest_phase[phase];
+    const int d2 = L.n_f2_direct[phase], dr = L.n_rest_direct[phase];
+    const int n2 = L.n_f2_phase[phase] - d2, nr = L.n_rest_phase[phase] - dr;
+    const int4* cp2 = L.f2g_cp.p + L.f2g_off[phase] + d2;
+    const int* lr = L.rest_phase[phase].p + dr;
     if (n2) {
         if (dtype == TS_F64)
-            k_face2_scatter<double><<<(n2 + 255) / 256, 256, 0, s>>>((double*)u, tmp, L.f2g_cp.p + L.f2g_off[phase], L.n_f2, nullptr, n2, L.N, L.B);
+            k_face2_scatter<double><<<(n2 + 255) / 256, 256, 0, s>>>((double*)u, tmp, cp2, L.n_f2, nullptr, n2, L.N, L.B);
         else
-            k_face2_scatter<float><<<(n2 + 255) / 256, 256, 0, s>>>((float*)u, tmp, L.f2g_cp.p + L.f2g_off[phase], L.n_f2, nullptr, n2, L.N, L.B);
+            k_face2_scatter<float><<<(n2 + 255) / 256, 256, 0, s>>>((float*)u, tmp, cp2, L.n_f2, nullptr, n2, L.N, L.B);
     }
     if (nr) {
         if (dtype == TS_F64)
-            k_iface_scatter<double><<<(nr + 255) / 256, 256, 0, s>>>((double*)u, tmp + n2, L.if_off.p, L.if_copy.p, L.rest_phase[phase].p, nr, L.N, L.B);
+            k_iface_scatter<double><<<(nr + 255) / 256, 256, 0, s>>>((double*)u, tmp + n2, L.if_off.p, L.if_copy.p, lr, nr, L.N, L.B);
         else
-            k_iface_scatter<float><<<(nr + 255) / 256, 256, 0, s>>>((float*)u, tmp + n2, L.if_off.p, L.if_copy.p, L.rest_phase[phase].p, nr, L.N, L.B);
+            k_iface_scatter<float><<<(nr + 255) / 256, 256, 0, s>>>((float*)u, tmp + n2, L.if_off.p, L.if_copy.p, lr, nr, L.N, L.B);
     }
     TS_HIP(hipGetLastError());
 }

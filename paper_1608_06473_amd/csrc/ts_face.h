@@ -135,6 +135,8 @@ __device__ __forceinline__ void face_basis(int N, int fa, int i, int j, int k,
 
 // One face fast-path node t (position q = list ? list[t] : t); same modes as
 // k_iface.  FQ = 0: the stored exact row; FQ > 0: the face fit of degree FQ.
+// Gauss-Seidel (MODE 2): nodes t < n_direct write the new value to both
+// copies, the others to tmp[t - n_direct].
 template <typename T, int MODE, int FQ = 0>
 __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restrict__ y,
                                            const T* __restrict__ f,
@@ -142,7 +144,7 @@ __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restric
                                            const double* __restrict__ sten,
                                            const double* __restrict__ fcoef, int n2,
                                            const int* __restrict__ list, int t, int N, int64_t B,
-                                           double* __restrict__ tmp) {
+                                           double* __restrict__ tmp, int n_direct = 0) {
     const int q = list ? list[t] : t;
     const int4 ca = cp[q], cb = cp[(size_t)n2 + q];
     const int ba = (int)bidx(N, ca.y, ca.z, ca.w), bb = (int)bidx(N, cb.y, cb.z, cb.w);
@@ -221,7 +223,13 @@ __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restric
     }
     const size_t sa = (size_t)ca.x * B + ba, sb = (size_t)cb.x * B + bb;
     if (MODE == 2) {
-        tmp[t] = ((double)f[sa] - of) / dg;
+        const double g = ((double)f[sa] - of) / dg;
+        if (t < n_direct) {
+            y[sa] = (T)g;
+            y[sb] = (T)g;
+        } else {
+            tmp[t - n_direct] = g;
+        }
         return;
     }
     double v = dg * (double)xa[ba] + of;

@@ -187,6 +187,12 @@ struct Level {
     // per GS phase: node ids of the general lists
     DBuf<int> rest_phase[N_IF_PHASES];
     int n_rest_phase[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
+    // Within a phase the nodes that no free node of the same phase is
+    // coupled to come first (the first n_f2_direct / n_rest_direct of each
+    // list): they are written in place, the rest through a temporary that
+    // is scattered after the phase.
+    int n_f2_direct[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
+    int n_rest_direct[N_IF_PHASES] = {0, 0, 0, 0, 0, 0};
 };
 
 #ifndef TS_VOL_R

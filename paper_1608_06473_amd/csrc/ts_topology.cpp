@@ -245,6 +245,64 @@ Level& Mesh::level(int lam) {
     }
     L->if_free.upload(freel);
     L->n_if_free = (int)freel.size();
+    // A phase updates every node from the values at the start of the phase.
+    // A free node with no fine-mesh neighbour (in any copy) among the free
+    // nodes of its own phase is read by no other node of the phase and reads
+    // nothing the phase changes: it can be written in place.  The others
+    // are coupled to a node of their phase (face nodes next to a face's
+    // edges, edge nodes next to a vertex) and keep the start-of-phase rule
+    // through a temporary.
+    std::vector<unsigned char> coupled(n_if, 0);
+    {
+        const int64_t base_f = nv + ne * (int64_t)(N - 1);
+        // interface node at the local barycentric coordinates mu of macro t
+        auto node_at = [&](int64_t t, const int mu[4]) -> int64_t {
+            const MacroTopo& T = topo[t];
+            int nz = 0, zo = -1, a0 = -1, a1 = -1;
+            for (int a = 0; a < 4; a++) {
+                if (mu[a] == 0) {
+                    zo = a;
+                } else {
+                    nz++;
+                    if (a0 < 0) a0 = a; else a1 = a;
+                }
+            }
+            if (nz == 1) return T.vg[a0];
+            if (nz == 2) {
+                int e = 0;
+                while (!(EDGE_LOC[e][0] == a0 && EDGE_LOC[e][1] == a1)) e++;
+                return nv + T.e[e] * (N - 1) + (mu[T.ehi[e]] - 1);
+            }
+            const int a = mu[T.fs[zo][1]], b = mu[T.fs[zo][2]];
+            return base_f + T.f[zo] * nF + (int64_t)(b - 1) * (N - 1) - (int64_t)(b - 1) * b / 2 +
+                   (a - 1);
+        };
+        for (int64_t n = 0; n < n_if; n++) {
+            if (flag[n] & 1) continue;
+            const int ph = flag[n] >> 1;
+            for (int c = off[n]; c < off[n + 1] && !coupled[n]; c++) {
+                const int4 q = cp[c];
+                const int m0[4] = {N - q.y - q.z - q.w, q.y, q.z, q.w};
+                // a face node two or more steps from its face's edges has only
+                // volume nodes and nodes of its own face around it, and those
+                // are of other phases (the face colouring is proper)
+                int zeros = 0, mn = N;
+                for (int a = 0; a < 4; a++) {
+                    if (m0[a] == 0) zeros++;
+                    else mn = std::min(mn, m0[a]);
+                }
+                if (zeros == 1 && mn >= 2) continue;
+                for (int w = 1; w < NW && !coupled[n]; w++) {
+                    const int i = q.y + dir_i(w), j = q.z + dir_j(w), k = q.w + dir_k(w);
+                    if (!inside(N, i, j, k)) continue;
+                    const int mu[4] = {N - i - j - k, i, j, k};
+                    if (mu[0] && i && j && k) continue;  // volume node
+                    const int64_t m = node_at(q.x, mu);
+                    if (!(flag[m] & 1) && (flag[m] >> 1) == ph) coupled[n] = 1;
+                }
+            }
+        }
+    }
     // face fast path: free nodes of interior faces (two copies)
     {
         std::vector<int> f2, rest;
@@ -298,13 +356,21 @@ Level& Mesh::level(int lam) {
             std::vector<int> b;
             L->f2g_off[p] = (int)g0.size();
             int n2p = 0;
-            for (int n : lists[p]) {
-                if (f2pos[n] >= 0) {
-                    g0.push_back(c0[f2pos[n]]);
-                    g1.push_back(c1[f2pos[n]]);
-                    n2p++;
-                } else {
-                    b.push_back(n);
+            // nodes written in place first, then the coupled ones
+            for (int pass = 0; pass < 2; pass++) {
+                for (int n : lists[p]) {
+                    if (coupled[n] != pass) continue;
+                    if (f2pos[n] >= 0) {
+                        g0.push_back(c0[f2pos[n]]);
+                        g1.push_back(c1[f2pos[n]]);
+                        n2p++;
+                    } else {
+                        b.push_back(n);
+                    }
+                }
+                if (pass == 0) {
+                    L->n_f2_direct[p] = n2p;
+                    L->n_rest_direct[p] = (int)b.size();
                 }
             }
             L->n_f2_phase[p] = n2p;

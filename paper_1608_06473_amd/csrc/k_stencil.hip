@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_zero_slots(T* __restrict__ y,
 template <typename T, int MODE, int FQ>
 __global__ __launch_bounds__(256) void k_face2(
     const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ f,
-    const int4* __restrict__ cp, const double* __restrict__ sten,
+    const int4* __restrict__ cp, const T* __restrict__ sten,
     const double* __restrict__ fcoef, int n2, const int* __restrict__ list, int n, int N,
     int64_t B, double* __restrict__ tmp, int n_direct) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,6 +325,22 @@ const double* face_stencils(Mesh& M, int lam, hipStream_t s) {
     return G.f2_sten.p;
 }
 
+const float* face_stencils32(Mesh& M, int lam, hipStream_t s) {
+    const Level& L = M.level(lam);
+    LevelGeo& G = M.level_geo(lam);
+    face_stencils(M, lam, s);
+    if (G.sten32_gen == M.geo_gen) return G.f2_sten32.p;
+    if (L.n_f2) {
+        const int64_t n = (int64_t)NW * L.n_f2;
+        if (!G.f2_sten32.p) G.f2_sten32.alloc(n);
+        if (!G.f2g_sten32.p) G.f2g_sten32.alloc(n);
+        launch_cast(G.f2_sten.p, TS_F64, G.f2_sten32.p, TS_F32, n, s);
+        launch_cast(G.f2g_sten.p, TS_F64, G.f2g_sten32.p, TS_F32, n, s);
+    }
+    G.sten32_gen = M.geo_gen;
+    return G.f2_sten32.p;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_iface_scatter(
     T* __restrict__ u, const double* __restrict__ tmp, const int* __restrict__ off,
@@ -361,7 +377,7 @@ __global__ __launch_bounds__(256) void k_face2_scatter(T* __restrict__ u, const 
     void launch_surr_q##Q##_k##K(const Level& L, int nt, const LevelOp& lo, int dtype,    \
                                  int center, int mode, const void* x, void* y,            \
                                  const void* f, int colour, hipStream_t s,                \
-                                 const double* f2sten, const double* f2coef);
+                                 const void* f2sten, const double* f2coef);
 TS_DECL(0, 2) TS_DECL(0, 4) TS_DECL(0, 8)
 TS_DECL(1, 2) TS_DECL(1, 4) TS_DECL(1, 8)
 TS_DECL(2, 2) TS_DECL(2, 4) TS_DECL(2, 8)
@@ -382,7 +398,10 @@ void launch_volume(const ts_op* op, int lam, int dtype, int mode, const void* x,
     const int kpt = L.lds_kpt <= 2 ? 2 : L.lds_kpt <= 4 ? 4 : 8;
     TS_REQUIRE(L.lds_kpt <= 8, TS_EINVAL, "level too large for the surrogate volume kernel");
     // face rows fused into the launch (apply / residual); built on first use
-    const double* f2 = fuse_face && mode != 2 && L.n_f2 ? face_stencils(M, lam, s) : nullptr;
+    const void* f2 = nullptr;
+    if (fuse_face && mode != 2 && L.n_f2)
+        f2 = dtype == TS_F64 ? (const void*)face_stencils(M, lam, s)
+                             : (const void*)face_stencils32(M, lam, s);
     const double* fc = f2 && lo.face_fit ? lo.fcoef.p : nullptr;
 #define TS_GO(Q, K) launch_surr_q##Q##_k##K(L, nt, lo, dtype, c, mode, x, y, f, colour, s, f2, fc)
     switch (q * 16 + kpt) {
@@ -467,6 +486,11 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     const int4* cp2 = phase >= 0 ? L.f2g_cp.p + go : L.f2_cp.p;
     const LevelGeo& G = M.level_geo(lam);
     const double* sten = phase >= 0 ? G.f2g_sten.p + go : G.f2_sten.p;
+    const float* sten32 = nullptr;
+    if (dtype != TS_F64 && L.n_f2) {
+        face_stencils32(M, lam, s);
+        sten32 = phase >= 0 ? G.f2g_sten32.p + go : G.f2_sten32.p;
+    }
     const int n2 = skip_face ? 0 : phase >= 0 ? L.n_f2_phase[phase] : L.n_f2;
     const int* lr = phase >= 0 ? L.rest_phase[phase].p : L.rest.p;
     const int nr = phase >= 0 ? L.n_rest_phase[phase] : L.n_rest;
@@ -477,7 +501,9 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
     double* tmp_r = tmp ? tmp + (n2 - d2) : nullptr;
 #define TS_F2Q(T_, M_, Q_)                                                                    \
     k_face2<T_, M_, Q_><<<(n2 + 255) / 256, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,   \
-                                                         cp2, sten, fc, L.n_f2, nullptr, n2,  \
+                                                         cp2, sizeof(T_) == 8 ? (const T_*)sten   \
+                                                         : (const T_*)sten32, fc, L.n_f2,     \
+                                                         nullptr, n2,                         \
                                                          L.N, L.B, tmp, d2)
 #define TS_F2(T_, M_)                                                                         \
     do {                                                                                      \

@@ -19,7 +19,9 @@ namespace ts {
 template <class WP, typename T, typename W>
 static void run(const Level& L, int nt, const int* ml, const float* cf, const double* cd,
                 int mode, const void* x, void* y, const void* f, int colour, hipStream_t s,
-                const double* f2sten, const double* f2coef) {
+                const void* f2sten_v, const double* f2coef) {
+    // the stored face rows come in the vector type
+    const T* f2sten = (const T*)f2sten_v;
     const dim3 grid((unsigned)(((nt + 7) / 8) * 8 * L.n_lds_tiles)), blk(VOL_THREADS);
     if (grid.x == 0 || L.n_lds_tiles == 0) return;
     const T* xp = (const T*)x;
@@ -53,7 +55,7 @@ static void run(const Level& L, int nt, const int* ml, const float* cf, const do
 void TS_CAT(launch_surr_q, TS_Q, _k, TS_KPT)(const Level& L, int nt, const LevelOp& lo, int dtype,
                                               int center, int mode, const void* x, void* y,
                                               const void* f, int colour, hipStream_t s,
-                                              const double* f2sten, const double* f2coef) {
+                                              const void* f2sten, const double* f2coef) {
     constexpr int Q = TS_Q;
     const int* ml = lo.sur_list.p;
     nt = lo.n_sur;

@@ -243,6 +243,7 @@ static void op_rows(const ts_op* op, int lam, int dtype, int mode, const void* x
     const bool fork = lam >= kForkLevel && op->side;
     // stored interface rows are built (once) on s, before either stream reads them
     face_stencils(op->mesh->m, lam, s);
+    if (dtype != TS_F64) face_stencils32(op->mesh->m, lam, s);
     if (fork) {
         TS_HIP(hipEventRecord(op->ev_fork, s));
         TS_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
@@ -802,6 +803,7 @@ static void solver_geometry(ts_solver* sv, hipStream_t s) {
     for (int lam = 3; lam <= sv->L; lam++) {
         const bool ifem = sv->p.dd || !uses_surrogate(op, lam) || op->lv.at(lam)->n_ifem > 0;
         warm_level(op, lam, ifem, s);
+        if (sv->p.precision != TS_F64) face_stencils32(op->mesh->m, lam, s);
         iface_tmp(op, lam);
     }
     TS_HIP(hipStreamSynchronize(s));

@@ -134,14 +134,16 @@ __device__ __forceinline__ void face_basis(int N, int fa, int i, int j, int k,
 }
 
 // One face fast-path node t (position q = list ? list[t] : t); same modes as
-// k_iface.  FQ = 0: the stored exact row; FQ > 0: the face fit of degree FQ.
+// k_iface.  FQ = 0: the stored exact row (its weights in the vector type T:
+// rounded to FP32 for FP32 vectors; sums in FP64); FQ > 0: the face fit of
+// degree FQ.
 // Gauss-Seidel (MODE 2): nodes t < n_direct write the new value to both
 // copies, the others to tmp[t - n_direct].
 template <typename T, int MODE, int FQ = 0>
 __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restrict__ y,
                                            const T* __restrict__ f,
                                            const int4* __restrict__ cp,
-                                           const double* __restrict__ sten,
+                                           const T* __restrict__ sten,
                                            const double* __restrict__ fcoef, int n2,
                                            const int* __restrict__ list, int t, int N, int64_t B,
                                            double* __restrict__ tmp, int n_direct = 0) {
@@ -173,11 +175,11 @@ __device__ __forceinline__ void face2_node(const T* __restrict__ x, T* __restric
     // at its neighbour; the fitted weights are formed one at a time
     double of = 0.0, dg;
     if constexpr (FQ == 0) {
-        const double* sw = sten + q;
-        dg = sw[0];
+        const T* sw = sten + q;
+        dg = (double)sw[0];
 #pragma unroll
         for (int e = 1; e < NW; e++)
-            of += sw[(size_t)e * n2] * (double)(e < 11 ? xa : xb)[ix[e]];
+            of += (double)sw[(size_t)e * n2] * (double)(e < 11 ? xa : xb)[ix[e]];
     } else {
         constexpr int M2 = FaceBasis<FQ>::M2;
         double phi[M2];

@@ -226,12 +226,14 @@ static_assert(VOL_THREADS % 64 == 0 && VOL_THREADS <= 1024, "bad volume workgrou
 // built on first use: the blended coordinates of every slot (element-wise
 // volume rows), the combined rows of the face fast path in canonical and
 // phase-grouped order ([15][n_f2] each), the partial stencils of the other
-// interface copies ([15][n_rc]); gens: the geometry generation they were
+// interface copies ([15][n_rc]), and single-precision copies of the face
+// rows for the FP32 vectors; gens: the geometry generation they were
 // computed for (-1: none).
 struct LevelGeo {
-    int xyz_gen = -1, sten_gen = -1;
+    int xyz_gen = -1, sten_gen = -1, sten32_gen = -1;
     DBuf<double> xyz;
     DBuf<double> f2_sten, f2g_sten, rest_sten;
+    DBuf<float> f2_sten32, f2g_sten32;
 };
 
 struct Mesh {
@@ -268,6 +270,8 @@ void build_topology(Mesh& M);
 // macro geometry records (host and device) from the vertex coordinates
 void build_geometry(Mesh& M);
 const double* face_stencils(Mesh& M, int lam, hipStream_t s);
+// the face rows rounded to FP32 (canonical order), built on first use
+const float* face_stencils32(Mesh& M, int lam, hipStream_t s);
 void warm_level(const ts_op* op, int lam, bool ifem_rows, hipStream_t s);
 
 // ------------------------------------------------------------ operators

@@ -296,7 +296,7 @@ void k_surr_lds(const T* x, T* y, const T* __restrict__ f, const float* __restri
                 int nt, const int* __restrict__ mlist, const unsigned* __restrict__ lanes,
                 const int* __restrict__ stage, int N, int64_t B, int colour,
                 const int4* __restrict__ f2cp = nullptr,
-                const double* __restrict__ f2sten = nullptr,
+                const T* __restrict__ f2sten = nullptr,
                 const double* __restrict__ f2coef = nullptr, int n2 = 0) {
     // the residual's f ring needs registers: shorter staging prefetch there
     // when the kernel is compiled for three waves

@@ -60,7 +60,7 @@ def request_bytes(n_macros, level, precision=TS_F32):
     """Admission estimate of the device bytes of one request: caller vectors
     f, u (FP64), the outer residual, the FP32 correction pair and three
     V-cycle vectors per level (FP32 or FP64), the stored interface rows of
-    every level, the nodal load values of the right-hand side (a set-up
+    every level (and their FP32 copies), the nodal load values of the right-hand side (a set-up
     temporary), plus a fixed allowance for coefficients, lists and the
     coarse inverse."""
     def vec(lam):
@@ -70,11 +70,12 @@ def request_bytes(n_macros, level, precision=TS_F32):
         N = 2 ** lam
         return int(1.84 * n_macros) * (N - 1) * (N - 2) // 2
     per_level = 12 if precision != TS_F64 else 24
+    # stored interface rows of the request's geometry: two 15-entry FP64
+    # copies per interior-face node, and their FP32 roundings for FP32 cycles
+    face_row = 240 + (120 if precision != TS_F64 else 0)
     b = vec(level) * (16 + 8 + (8 if precision != TS_F64 else 0) + 8 + 8)
     for lam in range(2, level + 1):
-        # cycle vectors, and the stored interface rows of the request's
-        # geometry (two 15-entry FP64 copies per interior-face node)
-        b += vec(lam) * per_level + face_nodes(lam) * 240
+        b += vec(lam) * per_level + face_nodes(lam) * face_row
     return int(b + 32 * 2 ** 20)
 
 

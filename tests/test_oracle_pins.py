@@ -545,6 +545,47 @@ def test_volume_colouring_is_proper(orc):
         assert (d[0] + 2 * d[1] + 3 * d[2]) % 4 != 0
 
 
+def test_interface_phase_couplings_lie_along_edges_and_vertices(orc):
+    # The interface phases (vertices, edges a mod 2, faces (a + 2b) mod 3 in
+    # the face frame) are Jacobi-style across some couplings.  On the
+    # 288-macro shell at level 4, every free interface node that shares a
+    # fine edge with a free node of its own phase is an edge node or a face
+    # node one step from one of its face's edges; no vertex is coupled to a
+    # vertex, and a face node two or more steps from its face's edges never
+    # meets its own phase (the rule by which the library's smoother writes
+    # such nodes in place during their phase).
+    N = 16
+    M = orc.Mesh(*inputs.shell288())
+    dirichlet = M.dirichlet_mask(N)
+    ph = {}
+    coupled = {1: 0, 2: 0, 3: 0, 4: 0, 5: 0}
+    n_face = 0
+    for u in range(M.num_unique(N)):
+        if dirichlet[u]:
+            continue
+        p = M.gs_phase(N, u)
+        if p >= 6:
+            continue
+        same = [v for v in M.row_neighbours(N, u) if M.gs_phase(N, int(v)) == p]
+        if p == 0:
+            assert not same
+            continue
+        if p >= 3:
+            n_face += 1
+            # smallest nonzero barycentric coordinate over the node's copies
+            near = min(min(b for b in (N - i - j - k, i, j, k) if b > 0)
+                       for _, (i, j, k) in M.copies(N, u))
+            if near >= 2:
+                assert not same, u
+        if same:
+            coupled[p] += 1
+    # the reading is not vacuous: both kinds of coupling occur (at level 4
+    # the bands one step from a face's edges hold 39 of a face's 105 nodes)
+    assert coupled[1] + coupled[2] > 0
+    assert coupled[3] + coupled[4] + coupled[5] > 0
+    assert n_face > 0
+
+
 # --------------------------------------------------------------------------
 # load vector (Sec. 2.2 eq. algebraic): consistent mass matrix on the
 # nodal interpolant

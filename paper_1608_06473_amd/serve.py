@@ -204,12 +204,15 @@ class Server:
     estimate); yield_level: while any request of this level or below is being
     set up or solved, requests of higher levels get no new iterations (their
     kernels would otherwise sit between the small requests' many short
-    kernels on the shared hardware queues); None: off.
+    kernels on the shared hardware queues); None: off.  The default, 5,
+    serves levels 4 and 5 of a 4/s mix of levels 4-7 in 45 / 66 ms (p50)
+    instead of 106 / 145 ms, for about 10% more level-7 latency and 3.5%
+    less throughput when the GPU is saturated.
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
                  hbm_budget=160 * 2 ** 30, max_active=32, setup_workers=4, fallback_tol=0.25,
-                 keep=(), gc_batch=8, inflight_work=2.0, warm_levels=(), yield_level=None,
+                 keep=(), gc_batch=8, inflight_work=2.0, warm_levels=(), yield_level=5,
                  reserve_bytes=16 * 2 ** 30, resident=True):
         import torch
         self.torch = torch
@@ -586,8 +589,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--inflight-work", type=float, default=2.0)
     ap.add_argument("--max-active", type=int, default=32)
-    ap.add_argument("--yield-level", type=int, default=None,
-                    help="hold higher levels while requests up to this level are in flight")
+    ap.add_argument("--yield-level", type=int, default=5,
+                    help="hold higher levels while requests up to this level are in flight "
+                         "(0: off)")
     ap.add_argument("--no-resident", action="store_true",
                     help="build and release a solver per request")
     args = ap.parse_args()
@@ -598,7 +602,7 @@ def main():
                                  levels=tuple(range(lo, hi + 1)))
     srv = Server(topology=args.topology, precision=prec, rtol=args.rtol,
                  max_active=args.max_active, inflight_work=args.inflight_work,
-                 yield_level=args.yield_level, resident=not args.no_resident,
+                 yield_level=args.yield_level or None, resident=not args.no_resident,
                  warm_levels=tuple(range(lo, hi + 1)))
     try:
         _, summ = srv.run(trace, log=lambda m: print(m, file=sys.stderr, flush=True))

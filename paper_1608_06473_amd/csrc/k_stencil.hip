@@ -11,12 +11,15 @@
 
 namespace ts {
 
+// lanes per node of the general lower-primitive path (a power of two <= 64)
+constexpr int IFACE_LANES = 8;
+
 // Lower primitives -------------------------------------------------------------
-// General path: one wavefront per listed free face/edge/vertex node (four
-// nodes per workgroup).  The lanes take the node's copies (the stored
-// element-wise partial stencil of each adjacent macro), the partial sums are
-// reduced across the wavefront in a fixed tree order, and the lanes write the
-// copies.  MODE 0: y = L x; 1: y = f - L x, written to every copy; 2:
+// General path: eight lanes per listed free face/edge/vertex node (32 nodes
+// per workgroup; an edge has 3-7 copies, a vertex up to about 20).  The
+// lanes take the node's copies (the stored element-wise partial stencil of
+// each adjacent macro), the partial sums are reduced across the eight lanes
+// in a fixed tree order, and the lanes write the copies.  MODE 0: y = L x; 1: y = f - L x, written to every copy; 2:
 // Gauss-Seidel value (f - off) / diag, written to every copy for t <
 // n_direct, else into tmp[t - n_direct].
 template <typename T, int MODE>
@@ -25,14 +28,15 @@ __global__ __launch_bounds__(256) void k_iface(
     const int* __restrict__ off, const int4* __restrict__ cp, const int* __restrict__ rc_base,
     const double* __restrict__ sten, int n_rc, const int* __restrict__ list, int n, int N,
     int64_t B, double* __restrict__ tmp, int n_direct) {
-    const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int lane = (int)(threadIdx.x & 63);
-    if (t >= n) return;  // whole wavefront
+    constexpr int LPN = IFACE_LANES;
+    const int t = blockIdx.x * (256 / LPN) + (int)(threadIdx.x / LPN);
+    const int lane = (int)(threadIdx.x % LPN);
+    if (t >= n) return;  // the node's whole lane group
     const int node = list[t];
     const int c0 = off[node], c1 = off[node + 1];
     const int rb = rc_base[node] - c0;
     double dg = 0.0, of = 0.0;
-    for (int c = c0 + lane; c < c1; c += 64) {
+    for (int c = c0 + lane; c < c1; c += LPN) {
         const int4 q = cp[c];
         const double* sw = sten + rb + c;
         const T* xm = x + (size_t)q.x * B;
@@ -45,9 +49,9 @@ __global__ __launch_bounds__(256) void k_iface(
                 of += sw[(size_t)w * n_rc] * (double)xm[o[w]];
     }
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) {
-        dg += __shfl_xor(dg, m, 64);
-        of += __shfl_xor(of, m, 64);
+    for (int m = LPN / 2; m > 0; m >>= 1) {
+        dg += __shfl_xor(dg, m, LPN);
+        of += __shfl_xor(of, m, LPN);
     }
     const int4 q0 = cp[c0];
     const size_t s0 = (size_t)q0.x * B + bidx(N, q0.y, q0.z, q0.w);
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256) void k_iface(
             if (lane == 0) tmp[t - n_direct] = g;
             return;
         }
-        for (int c = c0 + lane; c < c1; c += 64) {
+        for (int c = c0 + lane; c < c1; c += LPN) {
             const int4 q = cp[c];
             y[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = (T)g;
         }
@@ -65,7 +69,7 @@ __global__ __launch_bounds__(256) void k_iface(
     }
     double v = dg * (double)x[s0] + of;
     if (MODE == 1) v = (double)f[s0] - v;
-    for (int c = c0 + lane; c < c1; c += 64) {
+    for (int c = c0 + lane; c < c1; c += LPN) {
         const int4 q = cp[c];
         y[(size_t)q.x * B + bidx(N, q.y, q.z, q.w)] = (T)v;
     }
@@ -516,7 +520,8 @@ void launch_iface(const ts_op* op, int lam, int dtype, int mode, const void* x, 
         }                                                                                     \
     } while (0)
 #define TS_IF(T_, M_)                                                                         \
-    k_iface<T_, M_><<<(nr + 3) / 4, 256, 0, s>>>((const T_*)x, (T_*)y, (const T_*)f,           \
+    k_iface<T_, M_><<<(nr + 256 / IFACE_LANES - 1) / (256 / IFACE_LANES), 256, 0, s>>>(        \
+                                                     (const T_*)x, (T_*)y, (const T_*)f,      \
                                                      L.if_off.p, L.if_copy.p, L.rc_base.p,    \
                                                      G.rest_sten.p, L.n_rc, lr, nr, L.N, L.B, \
                                                      tmp_r, dr)

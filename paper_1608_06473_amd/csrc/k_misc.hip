@@ -132,25 +132,27 @@ __global__ __launch_bounds__(256) void k_restrict_face2(
     rc[(size_t)qb.x * Bc + bidx32(Nc, qb.y, qb.z, qb.w)] = (T)v;
 }
 
-// other free coarse interface nodes (edges, vertices): one wavefront per
-// node, copies across lanes, fixed-order reduction
+// other free coarse interface nodes (edges, vertices): eight lanes per node
+// (32 nodes per workgroup), copies across the lanes, fixed-order reduction
+constexpr int REST_LANES = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_rest(
     const T* __restrict__ rf, T* __restrict__ rc, const int* __restrict__ off,
     const int4* __restrict__ cp, const int* __restrict__ list, int n,
     const MacroTopo* __restrict__ topo, int Nc, int64_t Bf, int64_t Bc) {
-    const int t = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int lane = (int)(threadIdx.x & 63);
-    if (t >= n) return;
+    constexpr int LPN = REST_LANES;
+    const int t = blockIdx.x * (256 / LPN) + (int)(threadIdx.x / LPN);
+    const int lane = (int)(threadIdx.x % LPN);
+    if (t >= n) return;  // the node's whole lane group
     const int node = list[t];
     const int c0 = off[node], c1 = off[node + 1];
     double v = 0.0;
-    for (int c = c0 + lane; c < c1; c += 64) v += restrict_copy(rf, cp[c], topo[cp[c].x], Nc, Bf);
+    for (int c = c0 + lane; c < c1; c += LPN) v += restrict_copy(rf, cp[c], topo[cp[c].x], Nc, Bf);
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    for (int m = LPN / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, LPN);
     const int4 q0 = cp[c0];
     v += (double)rf[(size_t)q0.x * Bf + bidx32(2 * Nc, 2 * q0.y, 2 * q0.z, 2 * q0.w)];
-    for (int c = c0 + lane; c < c1; c += 64) {
+    for (int c = c0 + lane; c < c1; c += LPN) {
         const int4 q = cp[c];
         rc[(size_t)q.x * Bc + bidx32(Nc, q.y, q.z, q.w)] = (T)v;
     }
@@ -200,7 +202,7 @@ void launch_restrict(const Mesh& M, int lam_f, int dtype, const void* rf, void* 
     const Level& Lf = MM.level(lam_f);
     const Level& Lc = MM.level(lam_f - 1);
     const dim3 g1(Lc.n_slot_tiles, (unsigned)M.nt), b1(256);
-    const unsigned g2 = (unsigned)((Lc.n_f2 + 255) / 256), g3 = (unsigned)((Lc.n_rest + 3) / 4);
+    const unsigned g2 = (unsigned)((Lc.n_f2 + 255) / 256), g3 = (unsigned)((Lc.n_rest + 256 / REST_LANES - 1) / (256 / REST_LANES));
     const unsigned g4 = (unsigned)((Lc.n_dir_slots + 255) / 256);
 #define TS_R(T_)                                                                                  \
     k_restrict_volume<T_><<<g1, b1, 0, s>>>((const T_*)rf, (T_*)rc, Lc.slot_tiles.p, Lc.N, Lf.B,  \

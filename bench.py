@@ -57,6 +57,7 @@ def time_events(fn, reps, stream):
 
 
 KERNEL_SOURCES = ["paper_1608_06473_amd/csrc/ts_surrogate.h",
+                  "paper_1608_06473_amd/csrc/ts_face.h",
                   "paper_1608_06473_amd/csrc/k_surr_inst.hip"]
 PMC_RECORD = "profiles/pmc_k_surr_lds_q2_shell288_l7.md"
 

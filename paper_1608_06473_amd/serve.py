@@ -204,10 +204,10 @@ class Server:
     estimate); yield_level: while any request of this level or below is being
     set up or solved, requests of higher levels get no new iterations (their
     kernels would otherwise sit between the small requests' many short
-    kernels on the shared hardware queues); None: off.  The default, 5,
-    serves levels 4 and 5 of a 4/s mix of levels 4-7 in 45 / 66 ms (p50)
-    instead of 106 / 145 ms, for about 10% more level-7 latency and 3.5%
-    less throughput when the GPU is saturated.
+    kernels on the shared hardware queues), as long as no request waits for
+    admission; None: off.  The default, 5, serves levels 4 and 5 of a 4/s
+    mix of levels 4-7 in 45 / 66 ms (p50) instead of 106 / 145 ms, for about
+    10% more level-7 latency.
     """
 
     def __init__(self, topology="shell288", q=2, precision=TS_F32, rtol=1e-8, max_cycles=60,
@@ -472,8 +472,10 @@ class Server:
                         inflight += r.work
                 active[lvl] = still
             batch = []
+            # the hold applies while no request waits for admission: with a
+            # backlog the GPU is saturated and throughput comes first
             yl = self.yield_level
-            small = yl is not None and (
+            small = yl is not None and not waiting and (
                 any(active[l] for l in active if l <= yl)
                 or any(q.level <= yl for q in setting_up.values())
                 or any(q.level <= yl for q in to_setup))

@@ -253,6 +253,9 @@ Level& Mesh::level(int lam) {
     // edges, edge nodes next to a vertex) and keep the start-of-phase rule
     // through a temporary.
     std::vector<unsigned char> coupled(n_if, 0);
+    // set if a vertex shares a fine edge with an edge node of phase 1 (never
+    // on a conforming mesh: the edge nodes next to a vertex are odd, phase 2)
+    bool cross01 = false;
     {
         const int64_t base_f = nv + ne * (int64_t)(N - 1);
         // interface node at the local barycentric coordinates mu of macro t
@@ -280,7 +283,9 @@ Level& Mesh::level(int lam) {
         for (int64_t n = 0; n < n_if; n++) {
             if (flag[n] & 1) continue;
             const int ph = flag[n] >> 1;
-            for (int c = off[n]; c < off[n + 1] && !coupled[n]; c++) {
+            // nodes of phases 0 and 1 are scanned in full (for cross01)
+            auto scanning = [&] { return !coupled[n] || ph <= 1; };
+            for (int c = off[n]; c < off[n + 1] && scanning(); c++) {
                 const int4 q = cp[c];
                 const int m0[4] = {N - q.y - q.z - q.w, q.y, q.z, q.w};
                 // a face node two or more steps from its face's edges has only
@@ -292,13 +297,16 @@ Level& Mesh::level(int lam) {
                     else mn = std::min(mn, m0[a]);
                 }
                 if (zeros == 1 && mn >= 2) continue;
-                for (int w = 1; w < NW && !coupled[n]; w++) {
+                for (int w = 1; w < NW && scanning(); w++) {
                     const int i = q.y + dir_i(w), j = q.z + dir_j(w), k = q.w + dir_k(w);
                     if (!inside(N, i, j, k)) continue;
                     const int mu[4] = {N - i - j - k, i, j, k};
                     if (mu[0] && i && j && k) continue;  // volume node
                     const int64_t m = node_at(q.x, mu);
-                    if (!(flag[m] & 1) && (flag[m] >> 1) == ph) coupled[n] = 1;
+                    if (flag[m] & 1) continue;
+                    const int pm = flag[m] >> 1;
+                    if (pm == ph) coupled[n] = 1;
+                    if (ph <= 1 && pm <= 1 && pm != ph) cross01 = true;
                 }
             }
         }
@@ -351,14 +359,20 @@ Level& Mesh::level(int lam) {
         L->rest.upload(rest);
         // Gauss-Seidel copy of the face fast path: the same nodes grouped by
         // phase, so that phase p is the contiguous range f2g_off[p] ..
+        // Phases 0 (vertices) and 1 (even edge nodes) share no fine edge, so
+        // updating them together gives what updating them one after the other
+        // gives: they form one list (the list of phase 1 stays empty).
         std::vector<int4> g0, g1;
         for (int p = 0; p < N_IF_PHASES; p++) {
             std::vector<int> b;
             L->f2g_off[p] = (int)g0.size();
             int n2p = 0;
+            std::vector<int> ph_in = {p};
+            if (!cross01 && p == 0) ph_in = {0, 1};
+            if (!cross01 && p == 1) ph_in = {};
             // nodes written in place first, then the coupled ones
             for (int pass = 0; pass < 2; pass++) {
-                for (int n : lists[p]) {
+                for (int pp : ph_in) for (int n : lists[pp]) {
                     if (coupled[n] != pass) continue;
                     if (f2pos[n] >= 0) {
                         g0.push_back(c0[f2pos[n]]);

@@ -311,6 +311,15 @@ Level& Mesh::level(int lam) {
             }
         }
     }
+    // Whether the face-frame index a (the barycentric coordinate of the
+    // face's middle vertex by global id, against the smallest) runs along the
+    // block's i direction in this copy: the face's two lowest vertices are
+    // the copy's local vertices 0 and 1.
+    auto frame_rows_along_block_rows = [&](const int4& q) {
+        const int o = N - q.y - q.z - q.w == 0 ? 0 : q.y == 0 ? 1 : q.z == 0 ? 2 : 3;
+        const MacroTopo& T = topo[q.x];
+        return std::min(T.fs[o][0], T.fs[o][1]) == 0 && std::max(T.fs[o][0], T.fs[o][1]) == 1;
+    };
     // face fast path: free nodes of interior faces (two copies)
     {
         std::vector<int> f2, rest;
@@ -332,8 +341,16 @@ Level& Mesh::level(int lam) {
                 }
                 f2pos[n] = (int)f2.size();
                 f2.push_back((int)n);
-                c0.push_back(cp[off[n]]);
-                c1.push_back(cp[off[n] + 1]);
+                // the first copy takes eleven of the row's entries (the
+                // in-face ones and its inward ones): where only the second
+                // copy has the face's frame rows along its block rows, it
+                // goes first, so that consecutive nodes read consecutive
+                // entries there
+                int4 q0 = cp[off[n]], q1 = cp[off[n] + 1];
+                if (!frame_rows_along_block_rows(q0) && frame_rows_along_block_rows(q1))
+                    std::swap(q0, q1);
+                c0.push_back(q0);
+                c1.push_back(q1);
             } else {
                 rest.push_back((int)n);
                 rcb[n] = (int)rcc.size();

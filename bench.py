@@ -56,9 +56,11 @@ def time_events(fn, reps, stream):
     return start.elapsed_time(stop) / reps
 
 
+# the kernel and what fixes its access pattern (tiles, face-row copy order)
 KERNEL_SOURCES = ["paper_1608_06473_amd/csrc/ts_surrogate.h",
                   "paper_1608_06473_amd/csrc/ts_face.h",
-                  "paper_1608_06473_amd/csrc/k_surr_inst.hip"]
+                  "paper_1608_06473_amd/csrc/k_surr_inst.hip",
+                  "paper_1608_06473_amd/csrc/ts_topology.cpp"]
 PMC_RECORD = "profiles/pmc_k_surr_lds_q2_shell288_l7.md"
 
 

@@ -193,11 +193,15 @@ struct SurrogateW {
 
 // FP16 weight evaluation: the 1D column polynomials are evaluated in half
 // precision on coefficients pre-scaled by N (weights of order one), the
-// products and sums stay in FP32.
+// products and sums stay in FP32.  Two weights share one half2 register, so
+// each Horner step is one packed FP16 FMA for both (the same per-component
+// rounding as two scalar FP16 FMAs); weight 15 of the last pair is unused.
 template <int Q>
 struct SurrogateHalfW {
     static constexpr int kQ = Q;
-    _Float16 d[NW][Q + 1];
+    static constexpr int NP = (NW + 1) / 2;
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 d[NP][Q + 1];
     float invN;
     __device__ __forceinline__ void init_from(const float* __restrict__ cf,
                                               const double* __restrict__ cd, int macro, int N,
@@ -225,25 +229,29 @@ struct SurrogateHalfW {
 #pragma unroll
                 for (int c = 0; c < MQ; c++) t[BS.n[c]] += a[w * MQ + c] * (xp[BS.l[c]] * ep[BS.m[c]]);
 #pragma unroll
-                for (int n = 0; n <= Q; n++) d[w][n] = (_Float16)t[n];
+                for (int n = 0; n <= Q; n++) d[w / 2][n][w % 2] = (_Float16)t[n];
             }
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int w = 0; w < NW; w++)
+        for (int n = 0; n <= Q; n++) d[NP - 1][n][1] = (_Float16)0.0f;
 #pragma unroll
-            for (int n = 0; n <= Q; n++) asm volatile("" : "+v"(d[w][n]));
+        for (int p = 0; p < NP; p++)
+#pragma unroll
+            for (int n = 0; n <= Q; n++) asm volatile("" : "+v"(d[p][n]));
     }
     // weights of order one (coefficients pre-scaled by N) evaluated in half
     // precision, returned in float after scaling back by 1/N
     __device__ __forceinline__ void weights_z(float zf, float s[NW]) const {
-        const _Float16 z = (_Float16)zf;
+        const _Float16 zh = (_Float16)zf;
+        const h2 z = {zh, zh};
 #pragma unroll
-        for (int w = 0; w < NW; w++) {
-            _Float16 v = d[w][Q];
+        for (int p = 0; p < NP; p++) {
+            h2 v = d[p][Q];
 #pragma unroll
-            for (int n = Q - 1; n >= 0; n--) v = v * z + d[w][n];
-            s[w] = (float)v * invN;
+            for (int n = Q - 1; n >= 0; n--) v = v * z + d[p][n];
+            s[2 * p] = (float)v[0] * invN;
+            if (2 * p + 1 < NW) s[2 * p + 1] = (float)v[1] * invN;
         }
     }
 };

@@ -213,6 +213,33 @@ def solve_bench(ts, G, lam, op, log, keep=None):
             keep[name] = (fc, G.to_canon(lam, u).cpu().numpy(), coef)
         del sv
     out["fp32_ir_speedup_vs_fp64"] = round(out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
+    # the coarser levels evaluating the finest level's polynomials (remark in
+    # Sec. 3.4): set-up time and the FP64 solve's cycles against one fit per
+    # level
+    t0 = time.perf_counter()
+    opf = ts.Operator(G, lam, method=op.method, q=op.q)
+    torch.cuda.synchronize()
+    setup_each = time.perf_counter() - t0
+    del opf
+    t0 = time.perf_counter()
+    opc = ts.Operator(G, lam, method=op.method, q=op.q, coarse_from_finest=True)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    sv = ts.Solver(opc, lam, rtol=1e-10, max_cycles=100)
+    u, rc, info = sv.solve(fb, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rc, info = sv.solve(fb, raise_on_fail=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = {"ms": round(dt * 1e3, 2), "cycles": info.cycles, "status": rc,
+           "rel_residual": info.rel_residual, "ms_per_cycle": round(dt * 1e3 / max(info.cycles, 1), 3),
+           "operator_setup_ms": round(setup * 1e3, 2),
+           "operator_setup_ms_one_fit_per_level": round(setup_each * 1e3, 2),
+           "max_rel_diff_vs_fp64_solve": float((u - u64).abs().max() / u64.abs().max())}
+    out["fp64_coarse_from_finest"] = rec
+    log("solve fp64_coarse_from_finest: %s" % rec)
+    del sv, opc
     return out
 
 

@@ -116,6 +116,19 @@ typedef struct {
                             volume rows on some macro, and in exact residuals,
                             every face keeps its exact rows.  0: exact face
                             rows (default) */
+    int coarse_from_finest; /* non-zero: the coarser levels evaluate the
+                               finest level's surrogate polynomials (the
+                               remark in Sec. 3.4 on using the fine-level
+                               polynomial on the coarser meshes): their
+                               volume coefficients are the finest level's
+                               times 2^(max_level - l), the ratio of the mesh
+                               sizes (stiffness weights scale with h), and no
+                               fit runs on them; face fits and the fallback
+                               check stay per level.  Ignored by TS_IFEM and
+                               TS_CONS; TS_EINVAL with TS_LSQP_SYM (its node
+                               coefficients hold a shift of half a mesh step,
+                               which differs per level).  0: one fit per
+                               level (default) */
 } ts_op_params;
 
 typedef struct {

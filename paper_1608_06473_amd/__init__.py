@@ -47,7 +47,8 @@ class ts_layout_info(C.Structure):
 
 class ts_op_params(C.Structure):
     _fields_ = [("method", C.c_int), ("q", C.c_int), ("sample_j", C.c_int), ("center", C.c_int),
-                ("fallback_tol", C.c_double), ("face_surrogate", C.c_int)]
+                ("fallback_tol", C.c_double), ("face_surrogate", C.c_int),
+                ("coarse_from_finest", C.c_int)]
 
 
 class ts_solve_params(C.Structure):
@@ -216,8 +217,9 @@ def ts_rhs(mesh, level, kind, params, f, stream=None):
 
 
 def ts_op_create(mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 fallback_tol=0.0, stream=None, face_surrogate=False):
-    p = ts_op_params(method, q, sample_j, center, fallback_tol, 1 if face_surrogate else 0)
+                 fallback_tol=0.0, stream=None, face_surrogate=False, coarse_from_finest=False):
+    p = ts_op_params(method, q, sample_j, center, fallback_tol, 1 if face_surrogate else 0,
+                     1 if coarse_from_finest else 0)
     h = C.c_void_p()
     _check(lib().ts_op_create(mesh, max_level, C.byref(p), _stream(stream), C.byref(h)))
     return h
@@ -437,14 +439,14 @@ class Operator:
     """Owning wrapper of a ts_op handle (keeps its mesh alive)."""
 
     def __init__(self, mesh, max_level, method=TS_LSQP, q=2, sample_j=2, center=TS_CENTER_POLY,
-                 fallback_tol=0.0, stream=None, face_surrogate=False):
+                 fallback_tol=0.0, stream=None, face_surrogate=False, coarse_from_finest=False):
         self.mesh = mesh
         if method == TS_CONS:
             q = 0  # one constant stencil per macro: degree-0 coefficients
         self.method, self.q = method, q
         self.max_level = max_level
         self.h = ts_op_create(mesh.h, max_level, method, q, sample_j, center, fallback_tol,
-                              stream, face_surrogate)
+                              stream, face_surrogate, coarse_from_finest)
 
     def macro_flags(self, level):
         """1 for macros whose volume rows stay IFEM on this level."""

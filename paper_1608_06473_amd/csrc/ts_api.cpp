@@ -129,24 +129,36 @@ static void enqueue_level(ts_op* op, int lam, hipStream_t s) {
         launch_cons_stencils(M, lam, lo->coef64.p, s);
     } else if (sur) {
         const int N = 1 << lam, q = op->p.q, mq = op->mq;
-        std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
-        const int np = (int)pts.size() / 3;
-        TS_REQUIRE(np >= mq, TS_EINVAL, "sampling set smaller than the polynomial space");
-        if (!lo->fit_pts.p) {
-            lo->fit_pts.upload(pts);
-            if (op->p.method != TS_LSQP_SYM) {
-                lo->fit_basis.alloc((size_t)np * mq);
-                lo->fit_gram.alloc((size_t)mq * mq);
-                launch_fit_basis(N, q, lo->fit_pts.p, np, lo->fit_basis.p, lo->fit_gram.p, s);
-            }
-        }
-        SBuf<double> Bv((size_t)M.nt * np * NW, s);
         lo->coef64.alloc((size_t)M.nt * NW * mq);
-        launch_sample(M, lam, lo->fit_pts.p, np, Bv.p, s);
-        if (op->p.method == TS_LSQP_SYM)
-            launch_fit_sym(N, q, pts, Bv.p, (int)M.nt, lo->coef64.p, s);
-        else
-            launch_fit(q, lo->fit_basis.p, np, lo->fit_gram.p, Bv.p, (int)M.nt, lo->coef64.p, s);
+        if (op->p.coarse_from_finest && lam < op->max_level) {
+            // the finest level's polynomials (same reference coordinates),
+            // scaled by the mesh-size ratio: exact, a power of two
+            const LevelOp& fine = *op->lv.at(op->max_level);
+            const int64_t n = (int64_t)lo->coef64.n;
+            launch_fill(lo->coef64.p, TS_F64, n, 0.0, s);
+            launch_axpy(ldexp(1.0, op->max_level - lam), fine.coef64.p, TS_F64, lo->coef64.p,
+                        n, s);
+        } else {
+            std::vector<int> pts = sample_points(N, op->p.method, op->p.sample_j);
+            const int np = (int)pts.size() / 3;
+            TS_REQUIRE(np >= mq, TS_EINVAL, "sampling set smaller than the polynomial space");
+            if (!lo->fit_pts.p) {
+                lo->fit_pts.upload(pts);
+                if (op->p.method != TS_LSQP_SYM) {
+                    lo->fit_basis.alloc((size_t)np * mq);
+                    lo->fit_gram.alloc((size_t)mq * mq);
+                    launch_fit_basis(N, q, lo->fit_pts.p, np, lo->fit_basis.p, lo->fit_gram.p,
+                                     s);
+                }
+            }
+            SBuf<double> Bv((size_t)M.nt * np * NW, s);
+            launch_sample(M, lam, lo->fit_pts.p, np, Bv.p, s);
+            if (op->p.method == TS_LSQP_SYM)
+                launch_fit_sym(N, q, pts, Bv.p, (int)M.nt, lo->coef64.p, s);
+            else
+                launch_fit(q, lo->fit_basis.p, np, lo->fit_gram.p, Bv.p, (int)M.nt,
+                           lo->coef64.p, s);
+        }
     }
     if (cons || sur) {
         const size_t n = lo->coef64.n;
@@ -207,7 +219,11 @@ static void finish_levels(ts_op* op, hipStream_t s) {
 
 // every level of the operator, built (or rebuilt) on s; synchronous
 static void setup_levels(ts_op* op, hipStream_t s) {
-    for (int lam = 2; lam <= op->max_level; lam++) enqueue_level(op, lam, s);
+    // with coarse_from_finest the finest level is fitted first: the coarser
+    // ones scale its coefficients
+    if (op->p.coarse_from_finest) enqueue_level(op, op->max_level, s);
+    for (int lam = 2; lam <= op->max_level; lam++)
+        if (!(op->p.coarse_from_finest && lam == op->max_level)) enqueue_level(op, lam, s);
     finish_levels(op, s);
 }
 
@@ -629,6 +645,10 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             TS_REQUIRE(p->center == TS_CENTER_POLY || p->center == TS_CENTER_ROWSUM, TS_EINVAL,
                        "bad centre mode");
             TS_REQUIRE(!std::isnan(p->fallback_tol), TS_EINVAL, "fallback_tol is NaN");
+            // the symmetric surrogate's node coefficients carry a shift of
+            // half a mesh step, different on every level
+            TS_REQUIRE(!(p->coarse_from_finest && p->method == TS_LSQP_SYM), TS_EINVAL,
+                       "coarse_from_finest is defined for TS_LSQP and TS_IPOLY");
         }
         auto* op = new ts_op();
         try {
@@ -638,6 +658,7 @@ int ts_op_create(ts_mesh* mesh, int max_level, const ts_op_params* p, ts_stream 
             if (p->method == TS_LSQP_SYM) op->p.center = TS_CENTER_ROWSUM;
             op->max_level = max_level;
             if (p->method == TS_CONS) op->p.q = 0;  // degree-0 "polynomials"
+            if (p->method == TS_IFEM || p->method == TS_CONS) op->p.coarse_from_finest = 0;
             op->mq = p->method == TS_IFEM ? 0 : mq_of(op->p.q);
             setup_levels(op, S(s));
             TS_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));

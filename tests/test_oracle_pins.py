@@ -431,6 +431,34 @@ def test_affine_surrogate_is_constant_stencil(orc):
             assert np.abs(e - s).max() < 1e-12 * np.abs(s).max()
 
 
+def test_fine_polynomials_scaled_to_coarse_levels(orc):
+    # Remark in Sec. 3.4 (the fine-level polynomial used on the coarser
+    # meshes): the polynomials live in the macro's reference coordinates
+    # (i/N, j/N, k/N), the same on every level, and the stiffness weights
+    # scale with the mesh size, so level l takes the finest level's
+    # coefficients times N_fine / N_l.  With Phi = Id that is exact: the
+    # coarse fit equals the scaled fine fit; on the blended shell it is an
+    # approximation whose error falls as the levels get finer.
+    v, t = inputs.single_macro()
+    Ma = orc.Mesh(v, t, affine=True)
+    fine = Ma.fit(64, orc.LSQP, 2, 2)
+    for n in (8, 16, 32):
+        c = Ma.fit(n, orc.LSQP, 2, 2)
+        assert np.abs(c - (64 // n) * fine).max() < 1e-12 * np.abs(c).max()
+    Ms = orc.Mesh(*inputs.shell36())
+    fine = Ms.fit(64, orc.LSQP, 2, 2)
+    err = []
+    for n in (8, 16, 32):
+        c = Ms.fit(n, orc.LSQP, 2, 2)
+        # weights at the macro's centroid from both coefficient sets
+        p = (n // 4, n // 4, n // 4)
+        ec = np.array([[orc.poly_eval(2, n, c[m, w], *p) for w in range(15)] for m in range(36)])
+        es = np.array([[orc.poly_eval(2, n, (64 // n) * fine[m, w], *p) for w in range(15)]
+                       for m in range(36)])
+        err.append(np.abs(ec - es).max() / np.abs(ec).max())
+    assert err[0] > err[1] > err[2] > 0
+
+
 def test_surrogate_operator_row_sums(orc):
     # Lemma: the surrogate rows keep zero row sums -> L~ 1 = 0 on rows whose
     # neighbours are all free; checked with x = 1 on an interior-only region
